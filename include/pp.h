@@ -1,0 +1,219 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) particle-particle Coulomb library.
+ *
+ * The library implements the electrostatic particle-particle (PP) model of
+ * arXiv 2502.10640 ("Comparison between electrostatic PP and PIC simulations
+ * on electron bunch expansion"), Sec. 2.1:
+ *   - the direct field sum over all macro-particle pairs, Eq. (B) built from
+ *     Coulomb's law Eq. (A), here with optional Plummer softening eps
+ *     (eps = 0 is Eq. (B) exactly):
+ *       E_i = k sum_{j != i, same bunch} (w q_j) (r_i - r_j) / (|r_i - r_j|^2 + eps^2)^(3/2),
+ *       k = 1 / (4 pi eps0);
+ *   - the acceleration a_i = (q_i / m_i) E_i of Eqs. (D)/(F) (the macro
+ *     weight w cancels);
+ *   - the Velocity Verlet push of Eqs. (G)/(H):
+ *       r(t+dt) = r + v dt + a dt^2 / 2,   v(t+dt) = v + [a(t) + a(t+dt)] dt / 2;
+ *   - the beam diagnostics of Sec. 2.2 / 3.2 (emittance Eq. (I), rms and
+ *     maximum of x and v_x) plus energy, momentum and centre of mass.
+ * Several independent bunches ("batched" runs: one macro-weight / time-step
+ * sweep of the paper per call) share one context; particles of different
+ * bunches do not interact.
+ *
+ * Conventions for every call
+ *   - Units are SI: m, m/s, C, kg, s, V/m, V, J.
+ *   - Device pointers are HIP device addresses on the device that was current
+ *     when pp_create ran; host pointers are ordinary process memory.
+ *   - Every call returns a pp_status; no exception, abort or exit crosses the
+ *     ABI.  On PP_ERR_INVALID_ARG nothing was enqueued and no state changed.
+ *     After PP_ERR_DEVICE or PP_ERR_OUT_OF_MEMORY from a call other than
+ *     pp_create the context is broken: later calls return PP_ERR_STATE and
+ *     only pp_destroy is valid.  pp_last_error gives a message.
+ *   - Work is enqueued on the context's stream and is asynchronous unless a
+ *     call says otherwise.  One context must not be used from two host threads
+ *     at once.  Different contexts are independent.
+ */
+#ifndef PP_MI355X_PP_H
+#define PP_MI355X_PP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PP_ABI_VERSION 1
+
+typedef struct pp_ctx pp_ctx; /* opaque; owns its device scratch */
+
+typedef enum {
+  PP_OK = 0,
+  PP_ERR_INVALID_ARG = 1,   /* bad argument; nothing happened            */
+  PP_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                  */
+  PP_ERR_DEVICE = 3,        /* a HIP call failed                         */
+  PP_ERR_NOT_FINITE = 4,    /* PP_CHECK found a non-finite r, v or a     */
+  PP_ERR_STATE = 5          /* context unusable after an earlier failure */
+} pp_status;
+
+/* Arithmetic of the pair sum.
+ *   PP_FP64  : every pair in FP64; per-particle field summed per j-tile and
+ *              the tile sums combined with compensated (two-sum) addition.
+ *   PP_MIXED : pair arithmetic in FP32 on positions split into FP32 high and
+ *              low parts (so separations keep ~48 bits), tile sums in FP32
+ *              combined across tiles by two-sum; the push, the accumulation
+ *              of chunk partials and all reductions stay in FP64. */
+typedef enum { PP_FP64 = 0, PP_MIXED = 1 } pp_precision;
+
+/* One bunch: particles [offset, offset + n) of the state arrays.  Bunches
+ * must be sorted by offset and must not overlap (gaps are allowed and are
+ * left untouched).  Sec. 2.1: all macro-particles of a bunch share one
+ * weight w (Q = q w, M = m w). */
+typedef struct {
+  int64_t offset;   /* >= 0                                   */
+  int64_t n;        /* >= 1 particles                          */
+  double weight;    /* w > 0, real particles per macro-particle */
+  double softening; /* eps >= 0 [m]; 0 is the bare Eq. (B)     */
+  double dt;        /* Velocity Verlet step > 0 [s]            */
+} pp_bunch;
+
+/* Particle state, device SoA of length n_total, FP64.  Borrowed: the caller
+ * owns the memory, which must outlive the context.  r and v are read and
+ * updated in place by pp_push / pp_step_batched; q and m are read only and
+ * must not change while the context lives (they are inspected at create).
+ * q is the real-particle charge, m the real-particle mass (> 0). */
+typedef struct {
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  const double *q;
+  const double *m;
+} pp_state;
+
+/* Diagnostics of one bunch (host record).  Averages <.> are plain means over
+ * the bunch's particles (uniform weight).  Per-axis arrays are [x, y, z]. */
+typedef struct {
+  int64_t step;                  /* steps taken since create              */
+  int64_t n;                     /* particles                             */
+  double time;                   /* step * dt [s]                         */
+  double kinetic;                /* sum (1/2) w m |v|^2 [J]               */
+  double potential;              /* (1/2) sum w q phi [J], phi softened   */
+  double total;                  /* kinetic + potential                   */
+  double momentum[3];            /* sum w m v                             */
+  double com[3];                 /* sum m r / sum m                       */
+  double com_velocity[3];        /* sum m v / sum m                       */
+  double emittance[3];           /* Eq. (I) on raw moments                */
+  double emittance_centered[3];  /* Eq. (I) on moments about the means    */
+  double x_rms[3];               /* <x^2>^(1/2) (raw)                     */
+  double x_max[3];               /* max x                                 */
+  double v_rms[3];               /* <v_x^2>^(1/2) (raw)                   */
+  double v_max[3];               /* max v_x                               */
+  int64_t nonfinite;             /* particles with non-finite r or v      */
+} pp_diag;
+
+/* Flags of pp_step_batched. */
+#define PP_GRAPH 1u    /* replay the step loop from captured hipGraphs            */
+#define PP_AUTOTUNE 2u /* time candidate tilings once and keep the fastest passing */
+#define PP_CHECK 4u    /* synchronise after the steps; PP_ERR_NOT_FINITE if any r,
+                          v or a is not finite                                  */
+
+/* Kernel tiling of the pair sum.  Any valid tiling gives a correct result
+ * (within the precision's tolerance); for one tiling results are bitwise
+ * reproducible run to run. */
+typedef struct {
+  int32_t i_per_lane;    /* receivers held in registers per lane: 1, 2, 4 or 8  */
+  int32_t sum_tile;      /* j per plain partial sum before the two-sum: 32..256,
+                            power of two                                        */
+  int32_t chunk_pairs_log2; /* j-chunk splitting: a receiver block's sources are
+                            split into chunks of about 2^chunk_pairs_log2 pair
+                            interactions (16..30).  The split depends only on
+                            the bunch's own size, so a bunch gives the same
+                            bits alone or in a batch.                           */
+  int32_t grid_per_cu;   /* persistent workgroups per compute unit, 1..16       */
+  int32_t graph_steps;   /* steps captured per hipGraph with PP_GRAPH, 1..1024   */
+} pp_tuning;
+
+/* Create a context over n_bunches bunches of a state of n_total particles.
+ * Inspects q and m on the device (FP64 reductions) to validate them and to
+ * pick per-bunch charge scaling; synchronises the stream once.
+ *   out         receives the context (host pointer, required)
+ *   bunches     host array of n_bunches entries, read only during the call
+ *   n_total     length of every state array; every bunch lies inside it
+ *   state       host pointer to the device pointers of the state
+ *   prec        PP_FP64 or PP_MIXED
+ *   hip_stream  hipStream_t every call enqueues on; NULL is the device's
+ *               legacy default stream (ordered with all blocking streams)
+ * Errors: PP_ERR_INVALID_ARG (null pointers, n < 1, bad offsets, w <= 0,
+ * eps < 0, dt <= 0, non-finite parameters, m <= 0 or non-finite q/m on the
+ * device), PP_ERR_OUT_OF_MEMORY, PP_ERR_DEVICE.  On error *out is NULL and
+ * pp_last_error(NULL) holds the message. */
+pp_status pp_create(pp_ctx **out, const pp_bunch *bunches, int32_t n_bunches, int64_t n_total,
+                    const pp_state *state, pp_precision prec, void *hip_stream);
+
+/* Field (and optionally potential) at the current positions, Eq. (B) with
+ * softening, written to caller-owned device arrays of length n_total (entries
+ * outside every bunch are not written).  phi = NULL skips the potential; with
+ * phi the self term j = i is excluded as in E.  Asynchronous. */
+pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi);
+
+/* Advance every bunch by n_steps >= 0 Velocity Verlet steps (Eqs. (G)/(H)),
+ * each step a plain sequence of kernel launches.  The acceleration at the
+ * current positions is computed first if it is not known (first call, or after
+ * pp_invalidate).  Asynchronous. */
+pp_status pp_push(pp_ctx *ctx, int64_t n_steps);
+
+/* Same trajectory as pp_push (bitwise, for the same tiling), driven by the
+ * batched scheduler: one persistent pair-sum kernel per step serving every
+ * bunch from one work list; with PP_GRAPH the steps are replayed from hipGraphs
+ * captured on first use; with PP_AUTOTUNE the tiling is chosen by timing
+ * candidates once (the choice is kept in the context); PP_CHECK as above.
+ * Asynchronous unless PP_AUTOTUNE runs a search or PP_CHECK is given. */
+pp_status pp_step_batched(pp_ctx *ctx, int64_t n_steps, uint32_t flags);
+
+/* Diagnostics of every bunch into out[0 .. n_bunches-1] (host memory).  Costs
+ * one potential evaluation (O(N^2) per bunch) and FP64 reductions in a fixed
+ * order; synchronises the stream. */
+pp_status pp_diagnostics(pp_ctx *ctx, pp_diag *out);
+
+/* Declare that the caller changed r or v (the cached acceleration and the
+ * step counter's meaning are reset: a(t) is recomputed on the next push). */
+pp_status pp_invalidate(pp_ctx *ctx);
+
+/* Read or replace the tiling.  Setting checks ranges (PP_ERR_INVALID_ARG). */
+pp_status pp_get_tuning(const pp_ctx *ctx, pp_tuning *out);
+pp_status pp_set_tuning(pp_ctx *ctx, const pp_tuning *tuning);
+
+/* Time one field evaluation of the current tiling with HIP events on the
+ * context stream (synchronises): *ms receives the average over n_reps
+ * evaluations of the pair-sum kernel alone; *pairs the ordered pair
+ * interactions per evaluation (sum over bunches of n (n - 1)). */
+pp_status pp_time_field(pp_ctx *ctx, int32_t n_reps, double *ms, double *pairs);
+
+/* Kernel timing of the pair sum inside pp_push / pp_step_batched.  With
+ * profiling on, every pair-sum launch made outside a hipGraph is bracketed by
+ * HIP events on the context stream. */
+typedef struct {
+  int64_t launches;  /* pair-sum launches timed since the last read   */
+  double total_ms;   /* sum of their durations [ms]                   */
+  double pairs;      /* ordered pair interactions per launch          */
+} pp_profile;
+pp_status pp_set_profiling(pp_ctx *ctx, int32_t enable);
+/* Synchronises, returns and resets the counters. */
+pp_status pp_get_profile(pp_ctx *ctx, pp_profile *out);
+
+/* Synchronise the context stream. */
+pp_status pp_sync(pp_ctx *ctx);
+
+/* Release every resource of the context (synchronises first).  NULL is a
+ * no-op.  Valid in every state; the context must not be used afterwards. */
+pp_status pp_destroy(pp_ctx *ctx);
+
+/* Last error message of ctx, or of the calling thread's last failed
+ * pp_create when ctx is NULL.  Never NULL; "" when there was none.  The
+ * string lives until the next call on the same context (or thread). */
+const char *pp_last_error(const pp_ctx *ctx);
+
+/* PP_ABI_VERSION of the loaded library. */
+int32_t pp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_MI355X_PP_H */

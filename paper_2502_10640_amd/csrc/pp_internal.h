@@ -1,0 +1,147 @@
+// pp_internal.h -- device data layout shared by the gfx950 kernels and the
+// host runtime of the PP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ppk {
+
+// Threads per workgroup of the pair-sum kernels; also the number of j
+// particles staged in LDS per tile (one global load per thread per tile).
+constexpr int WG = 256;
+constexpr int JT = WG;
+
+// Per-bunch constants in device memory.
+//   Mixed path: positions enter the pair sum as u = (r - origin) * scale with
+//   scale a power of two (exact), split into FP32 hi + lo; the field is
+//   E = kE * S with S = sum_j qt_j d_u / (|d_u|^2 + eps2s)^(3/2) and
+//   kE = k w qref scale^2, the potential phi = kPhi * Psi with
+//   kPhi = k w qref scale.
+//   FP64 path: unscaled SI positions, S = sum_j qt_j d / (|d|^2 + eps2)^(3/2),
+//   kE = k w qref, kPhi = k w qref.
+//   qt_j = q_j / qref (exactly 1 for a bunch of identical charges).
+struct BunchDev {
+  int64_t off;        // first particle in the state arrays
+  int64_t n;          // particles
+  double dt;          // time step [s]
+  double origin[3];   // mixed-path origin [m]
+  double scale;       // mixed-path scale [1/m], power of two
+  double qref;        // reference charge [C]
+  double kE;          // field factor (see above)
+  double kPhi;        // potential factor
+  double eps2;        // FP64 path: eps^2 [m^2]
+  float eps2s;        // mixed path: (eps * scale)^2
+  int32_t n_chunks;   // j-chunks the bunch's sources are split into
+  int64_t chunk_len;  // sources per chunk (multiple of JT but the last)
+  int64_t pbase;      // first partial-sum slot of the bunch
+};
+
+// One unit of pair work: receivers [i0, i0 + i_per_lane * WG) of bunch b
+// against the sources of chunk `chunk` of the same bunch.
+struct WorkItem {
+  int32_t b;
+  int32_t chunk;
+  int32_t i0;
+  int32_t pad;
+};
+
+struct PairArgs {
+  const BunchDev* bunches;
+  const WorkItem* items;
+  int32_t n_items;
+  int32_t* counter;        // persistent-kernel work counter (zeroed by the pack kernel)
+  // mixed-path source mirror, FP32 SoA over all particles
+  const float* xh; const float* yh; const float* zh;
+  const float* xl; const float* yl; const float* zl;
+  const float* qt;
+  // FP64-path sources
+  const double* x; const double* y; const double* z;
+  const double* qt64;
+  // partial sums: planes of length P (mixed: float planes Sx Sy Sz Cx Cy Cz Sp Cp;
+  // fp64: double planes Sx Sy Sz Cx Cy Cz Sp Cp)
+  float* pf;
+  double* pd;
+  int64_t P;
+};
+
+// Number of partial-sum planes (field hi, field compensation, potential).
+constexpr int N_PLANES = 8;
+
+struct PackArgs {
+  const BunchDev* bunches;
+  const int32_t* bid;      // bunch of each particle, -1 outside every bunch
+  int64_t n_total;
+  double *x, *y, *z;
+  const double *vx, *vy, *vz;
+  const double *ax, *ay, *az;
+  float *xh, *yh, *zh, *xl, *yl, *zl;
+  int32_t* counter;
+};
+
+enum FinalMode : int32_t {
+  FIN_FIELD = 0,   // write E (and phi) to output arrays
+  FIN_ACCEL = 1,   // a = (q/m) E
+  FIN_KICK = 2     // a' = (q/m) E; v += (a + a') dt / 2; a = a'
+};
+
+struct FinalArgs {
+  const BunchDev* bunches;
+  const int32_t* bid;
+  int64_t n_total;
+  const float* pf;
+  const double* pd;
+  int64_t P;
+  const double* q;
+  const double* m;
+  double *vx, *vy, *vz;
+  double *ax, *ay, *az;
+  double *ex, *ey, *ez, *phi;   // FIN_FIELD outputs (phi may be null)
+};
+
+// Diagnostics: per-bunch reduction record in device memory (doubles).
+enum DiagSlot : int32_t {
+  D_KIN = 0, D_POT, D_MSUM, D_P0, D_P1, D_P2,
+  D_MR0, D_MR1, D_MR2, D_MV0, D_MV1, D_MV2,
+  D_X0, D_X1, D_X2, D_V0, D_V1, D_V2,
+  D_XX0, D_XX1, D_XX2, D_VV0, D_VV1, D_VV2,
+  D_XV0, D_XV1, D_XV2,
+  D_NSUM,                       // number of sums of pass 1
+  D_XMAX0 = D_NSUM, D_XMAX1, D_XMAX2, D_VMAX0, D_VMAX1, D_VMAX2,
+  D_NONFIN,
+  D_N1,                         // record length of pass 1
+  // pass 2 (centred second moments)
+  D_CXX0 = D_N1, D_CXX1, D_CXX2, D_CVV0, D_CVV1, D_CVV2, D_CXV0, D_CXV1, D_CXV2,
+  D_NREC
+};
+constexpr int D_N2 = D_NREC - D_N1;
+
+struct DiagArgs {
+  const BunchDev* bunches;
+  const double *x, *y, *z, *vx, *vy, *vz, *q, *m, *phi;
+  const double* weight;   // per bunch
+  double* part;           // [n_bunches][G][D_N1] block partials
+  double* rec;            // [n_bunches][D_NREC] reduced record
+  int32_t G;              // blocks per bunch
+};
+
+}  // namespace ppk
+
+// Launchers (pp_kernels.hip).  Each returns the hipGetLastError() status.
+namespace ppk {
+hipError_t launch_pack(const PackArgs& a, bool drift, bool mixed, hipStream_t s);
+hipError_t launch_pair(const PairArgs& a, bool mixed, int i_per_lane, int sum_tile, bool uniform_q,
+                       bool with_phi, int grid, hipStream_t s);
+hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s);
+hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,
+                        float* qt, double* qt64, hipStream_t s);
+hipError_t launch_minmax(const BunchDev* bunches, int32_t n_bunches, const double* x, const double* y,
+                         const double* z, const double* q, const double* m, double* out, int32_t G,
+                         hipStream_t s);
+hipError_t launch_check_finite(const int32_t* bid, int64_t n_total, const double* const* arrays,
+                               int32_t n_arrays, int32_t* flag, hipStream_t s);
+hipError_t launch_diag(const DiagArgs& a, int32_t n_bunches, hipStream_t s);
+hipError_t launch_fill_bid(int32_t* bid, int64_t n_total, const BunchDev* bunches, int32_t n_bunches,
+                           hipStream_t s);
+int pair_regs_hint(bool mixed, int i_per_lane);
+}  // namespace ppk

@@ -1,0 +1,901 @@
+// pp_runtime.hip -- host runtime behind the C ABI of include/pp.h.
+//
+// Owns the context: argument validation, device scratch, the per-bunch
+// constants, the work list of the persistent pair-sum kernel, the step
+// sequence (drift+pack -> pair sum -> combine+kick), hipGraph replay of the
+// step loop, diagnostics, kernel timing and the tiling autotuner.
+#include "pp.h"
+#include "pp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using ppk::BunchDev;
+using ppk::WorkItem;
+
+namespace {
+
+// Coulomb constant from the CODATA 2018 vacuum permittivity.
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+const double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
+
+thread_local std::string g_create_error;
+
+struct Graph {
+  hipGraphExec_t exec = nullptr;
+  int64_t steps = 0;
+};
+
+}  // namespace
+
+struct pp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // capture-only stream
+  pp_precision prec = PP_MIXED;
+  int32_t nb = 0;
+  int64_t n_total = 0;
+  int cus = 256;
+  std::vector<pp_bunch> hb;
+  std::vector<BunchDev> hbd;
+  pp_state st{};
+  bool uniform_q = true;
+  double pairs = 0.0;  // ordered pairs per evaluation
+
+  BunchDev* dbunch = nullptr;
+  int32_t* bid = nullptr;
+  double *ax = nullptr, *ay = nullptr, *az = nullptr;
+  float* mir = nullptr;  // 7 planes: xh yh zh xl yl zl qt
+  double* qt64 = nullptr;
+  void* part = nullptr;
+  size_t part_bytes = 0;
+  int64_t P = 0;
+  WorkItem* items = nullptr;
+  size_t items_cap = 0;
+  int32_t n_items = 0;
+  int32_t* counter = nullptr;  // [0] work counter, [1] finite flag
+  double* phi = nullptr;       // diagnostics potential
+  double* dweight = nullptr;   // per-bunch weight
+  double* diag_buf = nullptr;
+  size_t diag_doubles = 0;
+  double** arrptr = nullptr;   // device table of state pointers for the finite check
+  double *cmp_buf = nullptr;   // autotune comparison buffers (lazy)
+  void* hpin = nullptr;        // pinned host staging for every host<->device copy
+  size_t hpin_bytes = 0;
+
+  pp_tuning tun{};
+  bool tuned = false;
+  bool a_valid = false;
+  int64_t step = 0;
+  Graph graph;
+
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+  double prof_ms = 0.0;
+  int64_t prof_n = 0;
+
+  std::string err;
+  bool broken = false;
+
+  float* xh() const { return mir; }
+  float* plane(int k) const { return mir + (size_t)k * (size_t)n_total; }
+  bool mixed() const { return prec == PP_MIXED; }
+  int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
+};
+
+namespace {
+
+pp_status set_err(pp_ctx* c, pp_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+pp_status dev_fail(pp_ctx* c, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  pp_status s = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PP_ERR_OUT_OF_MEMORY : PP_ERR_DEVICE;
+  if (c) c->broken = true;
+  return set_err(c, s, msg);
+}
+
+#define PP_HIP(c, call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return dev_fail((c), e_, #call); \
+  } while (0)
+
+pp_status usable(pp_ctx* c) {
+  if (!c) return set_err(nullptr, PP_ERR_INVALID_ARG, "null context");
+  if (c->broken) return set_err(c, PP_ERR_STATE, "context is broken by an earlier device failure: " + c->err);
+  return PP_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+// Host <-> device copies go through a pinned staging buffer owned by the
+// context, enqueued on the context stream and waited for before returning:
+// no asynchronous copy ever touches pageable memory.
+pp_status ensure_pin(pp_ctx* c, size_t bytes) {
+  if (bytes <= c->hpin_bytes) return PP_OK;
+  if (c->hpin) hipHostFree(c->hpin);
+  c->hpin = nullptr;
+  c->hpin_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 16);
+  PP_HIP(c, hipHostMalloc(&c->hpin, want, hipHostMallocDefault));
+  c->hpin_bytes = want;
+  return PP_OK;
+}
+
+pp_status h2d(pp_ctx* c, void* dst, const void* src, size_t bytes) {
+  pp_status s;
+  if (bytes == 0) return PP_OK;
+  if ((s = ensure_pin(c, bytes)) != PP_OK) return s;
+  std::memcpy(c->hpin, src, bytes);
+  PP_HIP(c, hipMemcpyAsync(dst, c->hpin, bytes, hipMemcpyHostToDevice, c->stream));
+  PP_HIP(c, hipStreamSynchronize(c->stream));
+  return PP_OK;
+}
+
+pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
+  pp_status s;
+  if (bytes == 0) return PP_OK;
+  if ((s = ensure_pin(c, bytes)) != PP_OK) return s;
+  PP_HIP(c, hipMemcpyAsync(c->hpin, src, bytes, hipMemcpyDeviceToHost, c->stream));
+  PP_HIP(c, hipStreamSynchronize(c->stream));
+  std::memcpy(dst, c->hpin, bytes);
+  return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Work list: items (bunch, j-chunk, first receiver), heaviest first.
+// ---------------------------------------------------------------------------
+pp_status build_items(pp_ctx* c) {
+  // kernels still in flight may read the old list and partial planes
+  PP_HIP(c, hipStreamSynchronize(c->stream));
+  const int K = c->k_eff();
+  const int64_t BI = (int64_t)K * ppk::WG;
+  const double wstar = std::ldexp(1.0, c->tun.chunk_pairs_log2);
+
+  struct Cand { WorkItem w; double cost; };
+  std::vector<Cand> cand;
+  int64_t pbase = 0;
+  for (int b = 0; b < c->nb; ++b) {
+    const int64_t n = c->hb[b].n;
+    const double full = (double)std::min(BI, n) * (double)n;
+    int64_t nch = (int64_t)std::llround(full / wstar);
+    const int64_t max_ch = (n + ppk::JT - 1) / ppk::JT;
+    nch = std::max<int64_t>(1, std::min(nch, max_ch));
+    int64_t per = (n + nch - 1) / nch;
+    int64_t chunk_len = ((per + ppk::JT - 1) / ppk::JT) * ppk::JT;
+    nch = (n + chunk_len - 1) / chunk_len;
+    BunchDev& B = c->hbd[b];
+    B.n_chunks = (int32_t)nch;
+    B.chunk_len = chunk_len;
+    B.pbase = pbase;
+    pbase += nch * n;
+    const int64_t nib = (n + BI - 1) / BI;
+    for (int64_t ib = 0; ib < nib; ++ib) {
+      for (int64_t ch = 0; ch < nch; ++ch) {
+        const int64_t ni = std::min(BI, n - ib * BI);
+        const int64_t nj = std::min(chunk_len, n - ch * chunk_len);
+        // host-side shape checks of what the kernel assumes
+        if (ni <= 0 || nj <= 0 || ib * BI > INT32_MAX || ch > INT32_MAX)
+          return set_err(c, PP_ERR_INVALID_ARG, "work list: bunch too large for 32-bit local indices");
+        cand.push_back({WorkItem{b, (int32_t)ch, (int32_t)(ib * BI), 0}, (double)ni * (double)nj});
+      }
+    }
+  }
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) { return x.cost > y.cost; });
+  if (cand.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "work list too long");
+  std::vector<WorkItem> items(cand.size());
+  for (size_t k = 0; k < cand.size(); ++k) items[k] = cand[k].w;
+  c->n_items = (int32_t)items.size();
+
+  // partial-sum planes
+  const size_t esz = c->mixed() ? sizeof(float) : sizeof(double);
+  const size_t need = (size_t)ppk::N_PLANES * (size_t)std::max<int64_t>(pbase, 1) * esz;
+  if (need > c->part_bytes) {
+    if (c->part) hipFree(c->part);
+    c->part = nullptr;
+    c->part_bytes = 0;
+    PP_HIP(c, hipMalloc(&c->part, need));
+    c->part_bytes = need;
+  }
+  c->P = pbase;
+  if (items.size() > c->items_cap) {
+    if (c->items) hipFree(c->items);
+    c->items = nullptr;
+    c->items_cap = 0;
+    PP_HIP(c, dalloc(&c->items, items.size()));
+    c->items_cap = items.size();
+  }
+  pp_status s;
+  if ((s = h2d(c, c->items, items.data(), items.size() * sizeof(WorkItem))) != PP_OK) return s;
+  return h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks.
+// ---------------------------------------------------------------------------
+ppk::PairArgs pair_args(pp_ctx* c) {
+  ppk::PairArgs a{};
+  a.bunches = c->dbunch;
+  a.items = c->items;
+  a.n_items = c->n_items;
+  a.counter = c->counter;
+  if (c->mixed()) {
+    a.xh = c->plane(0); a.yh = c->plane(1); a.zh = c->plane(2);
+    a.xl = c->plane(3); a.yl = c->plane(4); a.zl = c->plane(5);
+    a.qt = c->plane(6);
+    a.pf = (float*)c->part;
+  } else {
+    a.x = c->st.x; a.y = c->st.y; a.z = c->st.z;
+    a.qt64 = c->qt64;
+    a.pd = (double*)c->part;
+  }
+  a.P = c->P;
+  return a;
+}
+
+ppk::PackArgs pack_args(pp_ctx* c) {
+  ppk::PackArgs a{};
+  a.bunches = c->dbunch;
+  a.bid = c->bid;
+  a.n_total = c->n_total;
+  a.x = c->st.x; a.y = c->st.y; a.z = c->st.z;
+  a.vx = c->st.vx; a.vy = c->st.vy; a.vz = c->st.vz;
+  a.ax = c->ax; a.ay = c->ay; a.az = c->az;
+  if (c->mixed()) {
+    a.xh = c->plane(0); a.yh = c->plane(1); a.zh = c->plane(2);
+    a.xl = c->plane(3); a.yl = c->plane(4); a.zl = c->plane(5);
+  }
+  a.counter = c->counter;
+  return a;
+}
+
+ppk::FinalArgs final_args(pp_ctx* c) {
+  ppk::FinalArgs a{};
+  a.bunches = c->dbunch;
+  a.bid = c->bid;
+  a.n_total = c->n_total;
+  a.pf = (const float*)c->part;
+  a.pd = (const double*)c->part;
+  a.P = c->P;
+  a.q = c->st.q;
+  a.m = c->st.m;
+  a.vx = c->st.vx; a.vy = c->st.vy; a.vz = c->st.vz;
+  a.ax = c->ax; a.ay = c->ay; a.az = c->az;
+  return a;
+}
+
+int grid_size(pp_ctx* c) {
+  const int64_t g = (int64_t)c->cus * c->tun.grid_per_cu;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, c->n_items));
+}
+
+hipEvent_t take_event(pp_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// The three launches of one evaluation, on stream s.
+pp_status enqueue_pack(pp_ctx* c, bool drift, hipStream_t s) {
+  PP_HIP(c, ppk::launch_pack(pack_args(c), drift, c->mixed(), s));
+  return PP_OK;
+}
+
+pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (!e0 || !e1) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+    PP_HIP(c, hipEventRecord(e0, s));
+  }
+  PP_HIP(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
+                             grid_size(c), s));
+  if (timed) {
+    PP_HIP(c, hipEventRecord(e1, s));
+    c->ev_used.push_back({e0, e1});
+  }
+  return PP_OK;
+}
+
+pp_status enqueue_final(pp_ctx* c, ppk::FinalMode mode, double* ex, double* ey, double* ez, double* phi,
+                        hipStream_t s) {
+  ppk::FinalArgs a = final_args(c);
+  a.ex = ex; a.ey = ey; a.ez = ez; a.phi = phi;
+  PP_HIP(c, ppk::launch_final(a, c->mixed(), mode, s));
+  return PP_OK;
+}
+
+pp_status ensure_accel(pp_ctx* c) {
+  if (c->a_valid) return PP_OK;
+  pp_status s;
+  if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, false, c->stream, c->prof)) != PP_OK) return s;
+  if ((s = enqueue_final(c, ppk::FIN_ACCEL, nullptr, nullptr, nullptr, nullptr, c->stream)) != PP_OK) return s;
+  c->a_valid = true;
+  return PP_OK;
+}
+
+pp_status enqueue_step(pp_ctx* c, hipStream_t s, bool timed) {
+  pp_status r;
+  if ((r = enqueue_pack(c, true, s)) != PP_OK) return r;
+  if ((r = enqueue_pair(c, false, s, timed)) != PP_OK) return r;
+  return enqueue_final(c, ppk::FIN_KICK, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+void drop_graph(pp_ctx* c) {
+  if (c->graph.exec) hipGraphExecDestroy(c->graph.exec);
+  c->graph = Graph{};
+}
+
+pp_status capture_graph(pp_ctx* c, int64_t steps) {
+  drop_graph(c);
+  PP_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  pp_status st = PP_OK;
+  for (int64_t k = 0; k < steps && st == PP_OK; ++k) st = enqueue_step(c, c->cap, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (st != PP_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(c, e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate");
+  c->graph.exec = ex;
+  c->graph.steps = steps;
+  return PP_OK;
+}
+
+pp_status check_finite(pp_ctx* c) {
+  PP_HIP(c, hipMemsetAsync(c->counter + 1, 0, sizeof(int32_t), c->stream));
+  PP_HIP(c, ppk::launch_check_finite(c->bid, c->n_total, c->arrptr, 9, c->counter + 1, c->stream));
+  int32_t flag = 0;
+  pp_status s = d2h(c, &flag, c->counter + 1, sizeof(int32_t));
+  if (s != PP_OK) return s;
+  if (flag) return set_err(c, PP_ERR_NOT_FINITE, "non-finite position, velocity or acceleration");
+  return PP_OK;
+}
+
+bool valid_tuning(const pp_tuning& t, bool mixed) {
+  const int k = t.i_per_lane;
+  if (!(k == 1 || k == 2 || k == 4 || k == 8)) return false;
+  if (!mixed && k == 8) return false;
+  if (t.sum_tile < 32 || t.sum_tile > 256 || (t.sum_tile & (t.sum_tile - 1))) return false;
+  if (t.chunk_pairs_log2 < 16 || t.chunk_pairs_log2 > 30) return false;
+  if (t.grid_per_cu < 1 || t.grid_per_cu > 16) return false;
+  if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
+  return true;
+}
+
+pp_tuning default_tuning(bool mixed) {
+  pp_tuning t{};
+  t.i_per_lane = mixed ? 2 : 1;
+  t.sum_tile = 64;
+  t.chunk_pairs_log2 = 22;
+  t.grid_per_cu = 4;
+  t.graph_steps = 16;
+  return t;
+}
+
+pp_status apply_tuning(pp_ctx* c, const pp_tuning& t) {
+  c->tun = t;
+  drop_graph(c);
+  return build_items(c);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate search over (i_per_lane, sum_tile, grid_per_cu) by
+// timed field evaluations on the context's own bunches; a candidate must
+// reproduce the field of the starting tiling (relative L2 within the
+// precision's tolerance) to be kept.  Choices are cached in a text file
+// keyed by device, precision and problem size.
+// ---------------------------------------------------------------------------
+std::string tune_key(pp_ctx* c) {
+  const int lp = (int)std::lround(std::log2(std::max(1.0, c->pairs)));
+  const int lb = (int)std::lround(std::log2((double)c->nb));
+  std::ostringstream o;
+  o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v1";
+  std::string s = o.str();
+  for (auto& ch : s)
+    if (ch == ' ') ch = '_';
+  return s;
+}
+
+std::string tune_path() {
+  if (const char* e = std::getenv("PP_TUNE_CACHE")) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/pp_mi355x_tune.txt";
+}
+
+bool tune_lookup(const std::string& key, pp_tuning* t) {
+  std::ifstream f(tune_path());
+  std::string k;
+  pp_tuning v{};
+  bool found = false;
+  while (f >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps) {
+    if (k == key) { *t = v; found = true; }
+  }
+  return found;
+}
+
+void tune_store(const std::string& key, const pp_tuning& t) {
+  const std::string path = tune_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "'";
+    if (std::system(cmd.c_str()) != 0) return;
+  }
+  std::ofstream f(path, std::ios::app);
+  if (f)
+    f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
+      << t.graph_steps << "\n";
+}
+
+pp_status time_eval(pp_ctx* c, int reps, double* ms) {
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+  double tot = 0.0;
+  pp_status st = PP_OK;
+  for (int r = 0; r < reps && st == PP_OK; ++r) {
+    if ((st = enqueue_pack(c, false, c->stream)) != PP_OK) break;
+    PP_HIP(c, hipEventRecord(e0, c->stream));
+    if ((st = enqueue_pair(c, false, c->stream, false)) != PP_OK) break;
+    PP_HIP(c, hipEventRecord(e1, c->stream));
+    PP_HIP(c, hipEventSynchronize(e1));
+    float f = 0.f;
+    PP_HIP(c, hipEventElapsedTime(&f, e0, e1));
+    tot += f;
+  }
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  *ms = tot / std::max(1, reps);
+  return st;
+}
+
+pp_status field_into(pp_ctx* c, double* ex, double* ey, double* ez) {
+  pp_status s;
+  if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, false, c->stream, false)) != PP_OK) return s;
+  return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, nullptr, c->stream);
+}
+
+pp_status l2_rel(pp_ctx* c, const double* ref, const double* got, double* rel) {
+  // 3 * n_total doubles each; done on the host from a copy (set-up path only)
+  const size_t n = (size_t)c->n_total * 3;
+  std::vector<double> a(n), b(n);
+  pp_status s;
+  if ((s = d2h(c, a.data(), ref, n * sizeof(double))) != PP_OK) return s;
+  if ((s = d2h(c, b.data(), got, n * sizeof(double))) != PP_OK) return s;
+  double num = 0.0, den = 0.0;
+  for (size_t k = 0; k < n; ++k) {
+    const double d = b[k] - a[k];
+    num += d * d;
+    den += a[k] * a[k];
+  }
+  *rel = den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+  return PP_OK;
+}
+
+pp_status autotune(pp_ctx* c) {
+  const std::string key = tune_key(c);
+  pp_tuning cached{};
+  if (tune_lookup(key, &cached) && valid_tuning(cached, c->mixed())) {
+    c->tuned = true;
+    return apply_tuning(c, cached);
+  }
+  const size_t n3 = (size_t)c->n_total * 3;
+  if (!c->cmp_buf) PP_HIP(c, dalloc(&c->cmp_buf, 2 * n3));
+  double* ref = c->cmp_buf;
+  double* got = c->cmp_buf + n3;
+  pp_status s;
+  pp_tuning best = c->tun;
+  if ((s = apply_tuning(c, best)) != PP_OK) return s;
+  if ((s = field_into(c, ref, ref + c->n_total, ref + 2 * c->n_total)) != PP_OK) return s;
+  double best_ms = 0.0;
+  if ((s = time_eval(c, 1, &best_ms)) != PP_OK) return s;   // warm-up
+  if ((s = time_eval(c, 2, &best_ms)) != PP_OK) return s;
+  const double tol = c->mixed() ? 1e-6 : 1e-13;
+  auto trial = [&](pp_tuning t) -> pp_status {
+    if (!valid_tuning(t, c->mixed())) return PP_OK;
+    pp_status r;
+    if ((r = apply_tuning(c, t)) != PP_OK) return r;
+    double ms = 0.0;
+    if ((r = time_eval(c, 2, &ms)) != PP_OK) return r;
+    if (ms < best_ms * 0.98) {
+      if ((r = field_into(c, got, got + c->n_total, got + 2 * c->n_total)) != PP_OK) return r;
+      double rel = 0.0;
+      if ((r = l2_rel(c, ref, got, &rel)) != PP_OK) return r;
+      if (rel <= tol) { best = t; best_ms = ms; }
+    }
+    return PP_OK;
+  };
+  const int ks[] = {1, 2, 4, 8};
+  for (int k : ks) { pp_tuning t = best; t.i_per_lane = k; if ((s = trial(t)) != PP_OK) return s; }
+  const int tiles[] = {32, 64, 128, 256};
+  for (int ts : tiles) { pp_tuning t = best; t.sum_tile = ts; if ((s = trial(t)) != PP_OK) return s; }
+  const int gpc[] = {1, 2, 4, 8};
+  for (int g : gpc) { pp_tuning t = best; t.grid_per_cu = g; if ((s = trial(t)) != PP_OK) return s; }
+  if ((s = apply_tuning(c, best)) != PP_OK) return s;
+  tune_store(key, best);
+  c->tuned = true;
+  return PP_OK;
+}
+
+void free_all(pp_ctx* c) {
+  drop_graph(c);
+  auto f = [](void* p) { if (p) hipFree(p); };
+  f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
+  f(c->items); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
+  if (c->hpin) hipHostFree(c->hpin);
+  for (auto& e : c->ev_pool) hipEventDestroy(e);
+  for (auto& p : c->ev_used) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
+  if (c->cap) hipStreamDestroy(c->cap);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int32_t pp_abi_version(void) { return PP_ABI_VERSION; }
+
+const char* pp_last_error(const pp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, int64_t n_total,
+                    const pp_state* state, pp_precision prec, void* hip_stream) {
+  g_create_error.clear();
+  if (!out) return set_err(nullptr, PP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!bunches || n_bunches < 1) return set_err(nullptr, PP_ERR_INVALID_ARG, "need at least one bunch");
+  if (!state) return set_err(nullptr, PP_ERR_INVALID_ARG, "state is NULL");
+  if (prec != PP_FP64 && prec != PP_MIXED) return set_err(nullptr, PP_ERR_INVALID_ARG, "unknown precision");
+  if (n_total < 1) return set_err(nullptr, PP_ERR_INVALID_ARG, "n_total < 1");
+  const pp_state& S = *state;
+  if (!S.x || !S.y || !S.z || !S.vx || !S.vy || !S.vz || !S.q || !S.m)
+    return set_err(nullptr, PP_ERR_INVALID_ARG, "state has a NULL array");
+  int64_t prev_end = 0;
+  for (int b = 0; b < n_bunches; ++b) {
+    const pp_bunch& B = bunches[b];
+    char buf[160];
+    if (B.n < 1 || B.offset < prev_end || B.offset > n_total - B.n) {
+      std::snprintf(buf, sizeof buf, "bunch %d: offset/n out of order, overlapping or outside n_total", b);
+      return set_err(nullptr, PP_ERR_INVALID_ARG, buf);
+    }
+    if (B.n > (int64_t)INT32_MAX / 2) {
+      std::snprintf(buf, sizeof buf, "bunch %d: more than 2^30 particles", b);
+      return set_err(nullptr, PP_ERR_INVALID_ARG, buf);
+    }
+    if (!finite_pos(B.weight) || !finite_pos(B.dt) || !std::isfinite(B.softening) || B.softening < 0.0) {
+      std::snprintf(buf, sizeof buf, "bunch %d: need weight > 0, dt > 0, softening >= 0, all finite", b);
+      return set_err(nullptr, PP_ERR_INVALID_ARG, buf);
+    }
+    prev_end = B.offset + B.n;
+  }
+
+  pp_ctx* c = new (std::nothrow) pp_ctx();
+  if (!c) return set_err(nullptr, PP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->prec = prec;
+  c->nb = n_bunches;
+  c->n_total = n_total;
+  c->st = S;
+  c->hb.assign(bunches, bunches + n_bunches);
+  c->hbd.resize(n_bunches);
+  auto fail = [&](pp_status s) {
+    g_create_error = c->err;
+    free_all(c);
+    delete c;
+    return s;
+  };
+#define PP_CREATE_HIP(call)                                        \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return fail(dev_fail(c, e_, #call));     \
+  } while (0)
+
+  PP_CREATE_HIP(hipGetDevice(&c->device));
+  int cus = 0;
+  PP_CREATE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  c->cus = std::max(1, cus);
+  c->stream = (hipStream_t)hip_stream;  // NULL: the legacy default stream
+  PP_CREATE_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+
+  const size_t n = (size_t)n_total;
+  PP_CREATE_HIP(dalloc(&c->dbunch, (size_t)n_bunches));
+  PP_CREATE_HIP(dalloc(&c->dweight, (size_t)n_bunches));
+  PP_CREATE_HIP(dalloc(&c->bid, n));
+  PP_CREATE_HIP(dalloc(&c->ax, n));
+  PP_CREATE_HIP(dalloc(&c->ay, n));
+  PP_CREATE_HIP(dalloc(&c->az, n));
+  PP_CREATE_HIP(dalloc(&c->counter, 4));
+  PP_CREATE_HIP(dalloc(&c->arrptr, 9));
+  if (prec == PP_MIXED) PP_CREATE_HIP(dalloc(&c->mir, 7 * n));
+  else PP_CREATE_HIP(dalloc(&c->qt64, n));
+
+  for (int b = 0; b < n_bunches; ++b) {
+    BunchDev& B = c->hbd[b];
+    std::memset(&B, 0, sizeof B);
+    B.off = bunches[b].offset;
+    B.n = bunches[b].n;
+    B.dt = bunches[b].dt;
+    B.n_chunks = 1;
+    B.chunk_len = B.n;
+  }
+  std::vector<double> wts(n_bunches);
+  for (int b = 0; b < n_bunches; ++b) wts[b] = bunches[b].weight;
+  pp_status st0;
+  if ((st0 = h2d(c, c->dweight, wts.data(), wts.size() * sizeof(double))) != PP_OK) return fail(st0);
+  if ((st0 = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return fail(st0);
+  PP_CREATE_HIP(hipMemsetAsync(c->bid, 0xff, n * sizeof(int32_t), c->stream));  // -1: outside every bunch
+  PP_CREATE_HIP(hipMemsetAsync(c->ax, 0, n * sizeof(double), c->stream));
+  PP_CREATE_HIP(hipMemsetAsync(c->ay, 0, n * sizeof(double), c->stream));
+  PP_CREATE_HIP(hipMemsetAsync(c->az, 0, n * sizeof(double), c->stream));
+  PP_CREATE_HIP(hipMemsetAsync(c->counter, 0, 4 * sizeof(int32_t), c->stream));
+  PP_CREATE_HIP(ppk::launch_fill_bid(c->bid, n_total, c->dbunch, n_bunches, c->stream));
+  const double* tbl[9] = {S.x, S.y, S.z, S.vx, S.vy, S.vz, c->ax, c->ay, c->az};
+  if ((st0 = h2d(c, c->arrptr, tbl, sizeof tbl)) != PP_OK) return fail(st0);
+
+  // device reductions over the bunches: extents, charge range, mass check
+  const int G = 64;
+  const int MM = 12;
+  double* mm = nullptr;
+  PP_CREATE_HIP(dalloc(&mm, (size_t)n_bunches * MM * (G + 1)));
+  hipError_t e = ppk::launch_minmax(c->dbunch, n_bunches, S.x, S.y, S.z, S.q, S.m, mm, G, c->stream);
+  std::vector<double> ext((size_t)n_bunches * MM);
+  if (e != hipSuccess) {
+    hipFree(mm);
+    return fail(dev_fail(c, e, "set-up reduction"));
+  }
+  st0 = d2h(c, ext.data(), mm, ext.size() * sizeof(double));
+  hipFree(mm);
+  if (st0 != PP_OK) return fail(st0);
+
+  bool uniform = true;
+  for (int b = 0; b < n_bunches; ++b) {
+    const double* r = &ext[(size_t)b * MM];
+    char buf[160];
+    if (r[10] != 0.0) {
+      std::snprintf(buf, sizeof buf, "bunch %d: %.0f particles with non-finite r, q or m", b, r[10]);
+      c->err = buf;
+      return fail(PP_ERR_INVALID_ARG);
+    }
+    if (!(r[8] > 0.0)) {
+      std::snprintf(buf, sizeof buf, "bunch %d: mass must be > 0", b);
+      c->err = buf;
+      return fail(PP_ERR_INVALID_ARG);
+    }
+    BunchDev& B = c->hbd[b];
+    double half = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      B.origin[a] = 0.5 * (r[2 * a] + r[2 * a + 1]);
+      half = std::max(half, 0.5 * (r[2 * a + 1] - r[2 * a]));
+    }
+    half = std::max({half, bunches[b].softening, 1e-300});
+    const int ex2 = (int)std::ceil(std::log2(half));
+    B.scale = std::ldexp(1.0, -ex2);
+    const double qlo = r[6], qhi = r[7];
+    double qref = std::fabs(qhi) >= std::fabs(qlo) ? qhi : qlo;
+    if (qref == 0.0) qref = 1.0;
+    B.qref = qref;
+    if (qlo != qhi) uniform = false;
+    const double w = bunches[b].weight, eps = bunches[b].softening;
+    if (prec == PP_MIXED) {
+      B.kE = kCoulomb * w * qref * B.scale * B.scale;
+      B.kPhi = kCoulomb * w * qref * B.scale;
+      const double es = eps * B.scale;
+      B.eps2s = (float)(es * es);
+    } else {
+      B.kE = kCoulomb * w * qref;
+      B.kPhi = kCoulomb * w * qref;
+      B.eps2 = eps * eps;
+    }
+    c->pairs += (double)B.n * (double)(B.n - 1);
+  }
+  c->uniform_q = uniform;
+  if ((st0 = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return fail(st0);
+  PP_CREATE_HIP(ppk::launch_qprep(c->dbunch, c->bid, n_total, S.q, c->mixed() ? c->plane(6) : nullptr, c->qt64,
+                                  c->stream));
+  c->tun = default_tuning(c->mixed());
+  pp_status st = build_items(c);
+  if (st != PP_OK) return fail(st);
+#undef PP_CREATE_HIP
+  *out = c;
+  return PP_OK;
+}
+
+pp_status pp_field(pp_ctx* c, double* ex, double* ey, double* ez, double* phi) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (!ex || !ey || !ez) return set_err(c, PP_ERR_INVALID_ARG, "field outputs must not be NULL");
+  if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, phi != nullptr, c->stream, false)) != PP_OK) return s;
+  return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, phi, c->stream);
+}
+
+pp_status pp_push(pp_ctx* c, int64_t n_steps) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (n_steps < 0) return set_err(c, PP_ERR_INVALID_ARG, "n_steps < 0");
+  if ((s = ensure_accel(c)) != PP_OK) return s;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    if ((s = enqueue_step(c, c->stream, c->prof)) != PP_OK) return s;
+    ++c->step;
+  }
+  return PP_OK;
+}
+
+pp_status pp_step_batched(pp_ctx* c, int64_t n_steps, uint32_t flags) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (n_steps < 0) return set_err(c, PP_ERR_INVALID_ARG, "n_steps < 0");
+  if (flags & ~(PP_GRAPH | PP_AUTOTUNE | PP_CHECK)) return set_err(c, PP_ERR_INVALID_ARG, "unknown flag");
+  if ((flags & PP_AUTOTUNE) && !c->tuned) {
+    if ((s = autotune(c)) != PP_OK) return s;
+  }
+  if ((s = ensure_accel(c)) != PP_OK) return s;
+  int64_t left = n_steps;
+  if ((flags & PP_GRAPH) && left >= c->tun.graph_steps) {
+    if (!c->graph.exec || c->graph.steps != c->tun.graph_steps) {
+      if ((s = capture_graph(c, c->tun.graph_steps)) != PP_OK) return s;
+    }
+    while (left >= c->graph.steps) {
+      PP_HIP(c, hipGraphLaunch(c->graph.exec, c->stream));
+      left -= c->graph.steps;
+      c->step += c->graph.steps;
+    }
+  }
+  for (; left > 0; --left) {
+    if ((s = enqueue_step(c, c->stream, c->prof)) != PP_OK) return s;
+    ++c->step;
+  }
+  if (flags & PP_CHECK) return check_finite(c);
+  return PP_OK;
+}
+
+pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (!out) return set_err(c, PP_ERR_INVALID_ARG, "out is NULL");
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / c->nb));
+  if (!c->phi) PP_HIP(c, dalloc(&c->phi, (size_t)c->n_total));
+  const size_t need = (size_t)c->nb * ((size_t)G * ppk::D_N1 + ppk::D_NREC + 34);
+  if (need > c->diag_doubles) {
+    if (c->diag_buf) hipFree(c->diag_buf);
+    c->diag_buf = nullptr;
+    c->diag_doubles = 0;
+    PP_HIP(c, dalloc(&c->diag_buf, need));
+    c->diag_doubles = need;
+  }
+  if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, true, c->stream, false)) != PP_OK) return s;
+  if ((s = enqueue_final(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, c->phi, c->stream)) != PP_OK) return s;
+  ppk::DiagArgs d{};
+  d.bunches = c->dbunch;
+  d.x = c->st.x; d.y = c->st.y; d.z = c->st.z;
+  d.vx = c->st.vx; d.vy = c->st.vy; d.vz = c->st.vz;
+  d.q = c->st.q; d.m = c->st.m; d.phi = c->phi;
+  d.weight = c->dweight;
+  d.part = c->diag_buf + (size_t)c->nb * (ppk::D_NREC + 34);
+  d.rec = c->diag_buf;
+  d.G = G;
+  PP_HIP(c, ppk::launch_diag(d, c->nb, c->stream));
+  std::vector<double> res((size_t)c->nb * 34);
+  if ((s = d2h(c, res.data(), c->diag_buf + (size_t)c->nb * ppk::D_NREC, res.size() * sizeof(double))) != PP_OK)
+    return s;
+  for (int b = 0; b < c->nb; ++b) {
+    const double* r = &res[(size_t)b * 34];
+    pp_diag& o = out[b];
+    o.step = c->step;
+    o.n = c->hb[b].n;
+    o.time = (double)c->step * c->hb[b].dt;
+    std::memcpy(&o.kinetic, r, 33 * sizeof(double));
+    o.nonfinite = (int64_t)std::llround(r[33]);
+  }
+  return PP_OK;
+}
+
+pp_status pp_invalidate(pp_ctx* c) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  c->a_valid = false;
+  return PP_OK;
+}
+
+pp_status pp_get_tuning(const pp_ctx* c, pp_tuning* out) {
+  if (!c || !out) return PP_ERR_INVALID_ARG;
+  *out = c->tun;
+  return PP_OK;
+}
+
+pp_status pp_set_tuning(pp_ctx* c, const pp_tuning* t) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (!t || !valid_tuning(*t, c->mixed())) return set_err(c, PP_ERR_INVALID_ARG, "tuning out of range");
+  c->tuned = true;
+  return apply_tuning(c, *t);
+}
+
+pp_status pp_time_field(pp_ctx* c, int32_t n_reps, double* ms, double* pairs) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (n_reps < 1 || !ms) return set_err(c, PP_ERR_INVALID_ARG, "n_reps < 1 or ms NULL");
+  if ((s = time_eval(c, n_reps, ms)) != PP_OK) return s;
+  if (pairs) *pairs = c->pairs;
+  return PP_OK;
+}
+
+pp_status pp_set_profiling(pp_ctx* c, int32_t enable) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  c->prof = enable != 0;
+  return PP_OK;
+}
+
+pp_status pp_get_profile(pp_ctx* c, pp_profile* out) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  if (!out) return set_err(c, PP_ERR_INVALID_ARG, "out is NULL");
+  PP_HIP(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (auto& p : c->ev_used) {
+    float f = 0.f;
+    PP_HIP(c, hipEventElapsedTime(&f, p.first, p.second));
+    tot += f;
+    c->ev_pool.push_back(p.first);
+    c->ev_pool.push_back(p.second);
+  }
+  out->launches = (int64_t)c->ev_used.size();
+  out->total_ms = tot;
+  out->pairs = c->pairs;
+  c->ev_used.clear();
+  return PP_OK;
+}
+
+pp_status pp_sync(pp_ctx* c) {
+  pp_status s;
+  if ((s = usable(c)) != PP_OK) return s;
+  PP_HIP(c, hipStreamSynchronize(c->stream));
+  return PP_OK;
+}
+
+pp_status pp_destroy(pp_ctx* c) {
+  if (!c) return PP_OK;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return PP_OK;
+}
+
+}  // extern "C"
