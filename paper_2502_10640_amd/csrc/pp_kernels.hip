@@ -20,6 +20,10 @@
 #include <cfloat>
 #include <cmath>
 
+#ifndef PP_MIXED_WAVES_PER_EU
+#define PP_MIXED_WAVES_PER_EU 2
+#endif
+
 namespace ppk {
 namespace {
 
@@ -52,33 +56,44 @@ __device__ __forceinline__ void acc_mixed(const float4* __restrict__ sh, const f
                                           const float (&xl)[K], const float (&yl)[K], const float (&zl)[K],
                                           float eps2, float (&tx)[K], float (&ty)[K], float (&tz)[K],
                                           float (&tp)[K]) {
-#pragma unroll 4
+  // Stages run across the K receivers so that K independent pairs are in
+  // flight between a v_rsq_f32 and the first use of its result.
+#pragma unroll 2
   for (int jj = jb; jj < je; ++jj) {
     const float4 h = sh[jj];
     const float4 l = sl[jj];
+    float dx[K], dy[K], dz[K], r2[K], inv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float dx = (xh[k] - h.x) + (xl[k] - l.x);
-      const float dy = (yh[k] - h.y) + (yl[k] - l.y);
-      const float dz = (zh[k] - h.z) + (zl[k] - l.z);
-      float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+      dx[k] = (xh[k] - h.x) + (xl[k] - l.x);
+      dy[k] = (yh[k] - h.y) + (yl[k] - l.y);
+      dz[k] = (zh[k] - h.z) + (zl[k] - l.z);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      r2[k] = fmaf(dz[k], dz[k], fmaf(dy[k], dy[k], fmaf(dx[k], dx[k], eps2)));
       if (DIAG) {
         // self term j == i: rsq(+inf) = 0 removes it from E and phi
-        if (jbase + jj == li[k]) r2 = __builtin_inff();
+        if (jbase + jj == li[k]) r2[k] = __builtin_inff();
       }
-      const float inv = __builtin_amdgcn_rsqf(r2);
-      const float inv2 = inv * inv;
-      const float s = UQ ? inv2 * inv : (h.w * inv) * inv2;
-      tx[k] = fmaf(dx, s, tx[k]);
-      ty[k] = fmaf(dy, s, ty[k]);
-      tz[k] = fmaf(dz, s, tz[k]);
-      if (PHI) tp[k] += UQ ? inv : h.w * inv;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) inv[k] = __builtin_amdgcn_rsqf(r2[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float inv2 = inv[k] * inv[k];
+      const float s = UQ ? inv2 * inv[k] : (h.w * inv[k]) * inv2;
+      tx[k] = fmaf(dx[k], s, tx[k]);
+      ty[k] = fmaf(dy[k], s, ty[k]);
+      tz[k] = fmaf(dz[k], s, tz[k]);
+      if (PHI) tp[k] += UQ ? inv[k] : h.w * inv[k];
     }
   }
 }
 
 template <int K, bool UQ, bool PHI>
-__global__ __launch_bounds__(WG) void pair_mixed_kernel(PairArgs a, int32_t sum_tile) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PP_MIXED_WAVES_PER_EU)))
+void pair_mixed_kernel(PairArgs a, int32_t sum_tile) {
   __shared__ float4 s_hi[JT];
   __shared__ float4 s_lo[JT];
   __shared__ int s_item;
