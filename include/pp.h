@@ -128,6 +128,11 @@ typedef struct {
                             bits alone or in a batch.                           */
   int32_t grid_per_cu;   /* persistent workgroups per compute unit, 1..16       */
   int32_t graph_steps;   /* steps captured per hipGraph with PP_GRAPH, 1..1024   */
+  int32_t symmetric;     /* PP_MIXED only: 1 evaluates each unordered pair once
+                            (Newton's third law, Eq. (A) antisymmetry) in rounds
+                            of block pairs, i_per_lane 1, 2 or 4 (blocks of
+                            512 i_per_lane particles); 0 evaluates every ordered
+                            pair in the persistent kernel                       */
 } pp_tuning;
 
 /* Create a context over n_bunches bunches of a state of n_total particles.

@@ -68,6 +68,33 @@ struct PairArgs {
 // Number of partial-sum planes (field hi, field compensation, potential).
 constexpr int N_PLANES = 8;
 
+// Symmetric pair sum (Newton's third law): one rsq per unordered pair.  A bunch
+// is cut into blocks of SYM_WAVES * 64 * i_per_lane particles.  An item is the
+// receiver block I against the source block J != I (both sides accumulated),
+// or a diagonal item I == J (ordered pairs inside the block, self excluded).
+// Items are grouped into rounds: round d holds (I, I + d mod n_blocks), so in
+// one round every block receives exactly one receiver-side and one
+// source-side contribution; rounds run one launch after another, which fixes
+// the order of every addition.
+constexpr int SYM_WAVES = 8;
+constexpr int SYM_WG = SYM_WAVES * 64;
+constexpr int SYM_PLANES = 16;  // Si(xyz) Ci(xyz) Sj(xyz) Cj(xyz) Sip Cip Sjp Cjp
+
+struct SymItem {
+  int32_t b;
+  int32_t I;
+  int32_t J;
+  int32_t diag;
+};
+
+struct SymArgs {
+  const BunchDev* bunches;
+  const SymItem* items;
+  const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;
+  float* acc;   // SYM_PLANES planes of length P, indexed by particle
+  int64_t P;
+};
+
 struct PackArgs {
   const BunchDev* bunches;
   const int32_t* bid;      // bunch of each particle, -1 outside every bunch
@@ -97,6 +124,7 @@ struct FinalArgs {
   double *vx, *vy, *vz;
   double *ax, *ay, *az;
   double *ex, *ey, *ez, *phi;   // FIN_FIELD outputs (phi may be null)
+  int32_t sym;                  // partials are the symmetric accumulators
 };
 
 // Diagnostics: per-bunch reduction record in device memory (doubles).
@@ -133,6 +161,8 @@ hipError_t launch_pack(const PackArgs& a, bool drift, bool mixed, hipStream_t s)
 hipError_t launch_pair(const PairArgs& a, bool mixed, int i_per_lane, int sum_tile, bool uniform_q,
                        bool with_phi, int grid, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s);
+hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
+                      hipStream_t s);
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,
                         float* qt, double* qt64, hipStream_t s);
 hipError_t launch_minmax(const BunchDev* bunches, int32_t n_bunches, const double* x, const double* y,

@@ -15,6 +15,7 @@
 // chunk partials in chunk order in FP64.  No floating-point atomics anywhere;
 // the only atomic is the work counter, which decides who computes an item,
 // never the order of an addition.
+#include "pp_device.h"
 #include "pp_internal.h"
 
 #include <cfloat>
@@ -26,22 +27,6 @@
 
 namespace ppk {
 namespace {
-
-__device__ __forceinline__ void two_sum(float& s, float& c, float t) {
-  const float u = s + t;
-  const float bp = u - s;
-  const float err = (s - (u - bp)) + (t - bp);
-  s = u;
-  c += err;
-}
-
-__device__ __forceinline__ void two_sum(double& s, double& c, double t) {
-  const double u = s + t;
-  const double bp = u - s;
-  const double err = (s - (u - bp)) + (t - bp);
-  s = u;
-  c += err;
-}
 
 // ---------------------------------------------------------------------------
 // Mixed precision pair sum.  Separation d = (hi_i - hi_j) + (lo_i - lo_j):
@@ -357,7 +342,16 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   const int64_t li = i - B.off;
   const bool want_phi = (MODE == FIN_FIELD) && a.phi != nullptr;
   double ex = 0.0, ey = 0.0, ez = 0.0, ph = 0.0;
-  for (int c = 0; c < B.n_chunks; ++c) {
+  if (MIXED && a.sym) {
+    // receiver side (S, C) then source side (S, C), in that order
+    const float* f = a.pf;
+    const int64_t P = a.P;
+    ex = ((double)f[0 * P + i] + (double)f[3 * P + i]) + ((double)f[6 * P + i] + (double)f[9 * P + i]);
+    ey = ((double)f[1 * P + i] + (double)f[4 * P + i]) + ((double)f[7 * P + i] + (double)f[10 * P + i]);
+    ez = ((double)f[2 * P + i] + (double)f[5 * P + i]) + ((double)f[8 * P + i] + (double)f[11 * P + i]);
+    if (want_phi) ph = ((double)f[12 * P + i] + (double)f[13 * P + i]) + ((double)f[14 * P + i] + (double)f[15 * P + i]);
+  }
+  for (int c = 0; c < ((MIXED && a.sym) ? 0 : B.n_chunks); ++c) {
     const int64_t s = B.pbase + (int64_t)c * B.n + li;
     if (MIXED) {
       ex += (double)a.pf[0 * a.P + s] + (double)a.pf[3 * a.P + s];

@@ -69,6 +69,10 @@ struct pp_ctx {
   size_t diag_doubles = 0;
   double** arrptr = nullptr;   // device table of state pointers for the finite check
   double *cmp_buf = nullptr;   // autotune comparison buffers (lazy)
+  ppk::SymItem* sitems = nullptr;  // symmetric schedule: diagonal launch, then one launch per round
+  size_t sitems_cap = 0;
+  std::vector<std::pair<int32_t, int32_t>> launches;  // (first item, items) per launch
+  float* acc = nullptr;            // symmetric accumulators, SYM_PLANES x n_total
   void* hpin = nullptr;        // pinned host staging for every host<->device copy
   size_t hpin_bytes = 0;
 
@@ -90,6 +94,7 @@ struct pp_ctx {
   float* xh() const { return mir; }
   float* plane(int k) const { return mir + (size_t)k * (size_t)n_total; }
   bool mixed() const { return prec == PP_MIXED; }
+  bool sym() const { return prec == PP_MIXED && tun.symmetric != 0; }
   int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
 };
 
@@ -164,6 +169,48 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric schedule.  Blocks of SYM_WG * i_per_lane particles per bunch; launch
+// 0 holds every diagonal item, launch d >= 1 the block pairs (I, I + d mod nb)
+// (for even nb and d = nb/2 only I < nb/2), so each unordered block pair occurs
+// exactly once and no two items of a launch share an accumulator.
+// ---------------------------------------------------------------------------
+pp_status build_sym(pp_ctx* c) {
+  const int64_t BS = (int64_t)ppk::SYM_WG * c->tun.i_per_lane;
+  std::vector<ppk::SymItem> items;
+  c->launches.clear();
+  int64_t maxr = 0;
+  for (int b = 0; b < c->nb; ++b) {
+    const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
+    if (nbk > INT32_MAX / 2) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule: too many blocks");
+    for (int64_t I = 0; I < nbk; ++I) items.push_back({b, (int32_t)I, (int32_t)I, 1});
+    maxr = std::max(maxr, nbk / 2);
+  }
+  c->launches.push_back({0, (int32_t)items.size()});
+  for (int64_t d = 1; d <= maxr; ++d) {
+    const size_t first = items.size();
+    for (int b = 0; b < c->nb; ++b) {
+      const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
+      if (d > nbk / 2) continue;
+      for (int64_t I = 0; I < nbk; ++I) {
+        if (2 * d == nbk && I >= nbk / 2) continue;
+        items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), 0});
+      }
+    }
+    if (items.size() > first) c->launches.push_back({(int32_t)first, (int32_t)(items.size() - first)});
+  }
+  if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
+  if (items.size() > c->sitems_cap) {
+    if (c->sitems) hipFree(c->sitems);
+    c->sitems = nullptr;
+    c->sitems_cap = 0;
+    PP_HIP(c, dalloc(&c->sitems, items.size()));
+    c->sitems_cap = items.size();
+  }
+  if (!c->acc) PP_HIP(c, dalloc(&c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total));
+  return h2d(c, c->sitems, items.data(), items.size() * sizeof(ppk::SymItem));
+}
+
+// ---------------------------------------------------------------------------
 // Work list: items (bunch, j-chunk, first receiver), heaviest first.
 // ---------------------------------------------------------------------------
 pp_status build_items(pp_ctx* c) {
@@ -228,7 +275,8 @@ pp_status build_items(pp_ctx* c) {
   }
   pp_status s;
   if ((s = h2d(c, c->items, items.data(), items.size() * sizeof(WorkItem))) != PP_OK) return s;
-  return h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev));
+  if ((s = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return s;
+  return c->sym() ? build_sym(c) : PP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -275,9 +323,10 @@ ppk::FinalArgs final_args(pp_ctx* c) {
   a.bunches = c->dbunch;
   a.bid = c->bid;
   a.n_total = c->n_total;
-  a.pf = (const float*)c->part;
+  a.pf = c->sym() ? c->acc : (const float*)c->part;
   a.pd = (const double*)c->part;
-  a.P = c->P;
+  a.P = c->sym() ? c->n_total : c->P;
+  a.sym = c->sym() ? 1 : 0;
   a.q = c->st.q;
   a.m = c->st.m;
   a.vx = c->st.vx; a.vy = c->st.vy; a.vz = c->st.vz;
@@ -315,8 +364,21 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
     if (!e0 || !e1) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
     PP_HIP(c, hipEventRecord(e0, s));
   }
-  PP_HIP(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
-                             grid_size(c), s));
+  if (c->sym()) {
+    ppk::SymArgs sa{};
+    sa.bunches = c->dbunch;
+    sa.items = c->sitems;
+    sa.xh = c->plane(0); sa.yh = c->plane(1); sa.zh = c->plane(2);
+    sa.xl = c->plane(3); sa.yl = c->plane(4); sa.zl = c->plane(5);
+    sa.qt = c->plane(6);
+    sa.acc = c->acc;
+    sa.P = c->n_total;
+    for (const auto& L : c->launches)
+      PP_HIP(c, ppk::launch_sym(sa, L.first, L.second, c->tun.i_per_lane, c->uniform_q, phi, s));
+  } else {
+    PP_HIP(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
+                               grid_size(c), s));
+  }
   if (timed) {
     PP_HIP(c, hipEventRecord(e1, s));
     c->ev_used.push_back({e0, e1});
@@ -393,16 +455,30 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.chunk_pairs_log2 < 16 || t.chunk_pairs_log2 > 30) return false;
   if (t.grid_per_cu < 1 || t.grid_per_cu > 16) return false;
   if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
+  if (t.symmetric != 0 && t.symmetric != 1) return false;
+  if (t.symmetric && (!mixed || k == 8)) return false;
   return true;
 }
 
-pp_tuning default_tuning(bool mixed) {
+// Symmetric rounds pay off when every round keeps the GPU busy: the default
+// uses them when each bunch splits into at least 512 blocks.
+pp_tuning default_tuning(bool mixed, int64_t min_n) {
   pp_tuning t{};
   t.i_per_lane = mixed ? 2 : 1;
   t.sum_tile = 64;
   t.chunk_pairs_log2 = 22;
   t.grid_per_cu = 4;
   t.graph_steps = 16;
+  t.symmetric = 0;
+  if (mixed) {
+    for (int k : {4, 2, 1}) {
+      if (min_n >= (int64_t)512 * ppk::SYM_WG * k) {
+        t.symmetric = 1;
+        t.i_per_lane = k;
+        break;
+      }
+    }
+  }
   return t;
 }
 
@@ -424,7 +500,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v1";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v2";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -442,7 +518,8 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
   std::string k;
   pp_tuning v{};
   bool found = false;
-  while (f >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps) {
+  while (f >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
+         v.symmetric) {
     if (k == key) { *t = v; found = true; }
   }
   return found;
@@ -459,7 +536,7 @@ void tune_store(const std::string& key, const pp_tuning& t) {
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
-      << t.graph_steps << "\n";
+      << t.graph_steps << " " << t.symmetric << "\n";
 }
 
 pp_status time_eval(pp_ctx* c, int reps, double* ms) {
@@ -546,6 +623,16 @@ pp_status autotune(pp_ctx* c) {
   for (int ts : tiles) { pp_tuning t = best; t.sum_tile = ts; if ((s = trial(t)) != PP_OK) return s; }
   const int gpc[] = {1, 2, 4, 8};
   for (int g : gpc) { pp_tuning t = best; t.grid_per_cu = g; if ((s = trial(t)) != PP_OK) return s; }
+  if (c->mixed()) {
+    for (int sym : {0, 1}) {
+      for (int k : {1, 2, 4}) {
+        pp_tuning t = best;
+        t.symmetric = sym;
+        t.i_per_lane = k;
+        if ((s = trial(t)) != PP_OK) return s;
+      }
+    }
+  }
   if ((s = apply_tuning(c, best)) != PP_OK) return s;
   tune_store(key, best);
   c->tuned = true;
@@ -556,7 +643,7 @@ void free_all(pp_ctx* c) {
   drop_graph(c);
   auto f = [](void* p) { if (p) hipFree(p); };
   f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
-  f(c->items); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
+  f(c->items); f(c->sitems); f(c->acc); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
   if (c->hpin) hipHostFree(c->hpin);
   for (auto& e : c->ev_pool) hipEventDestroy(e);
   for (auto& p : c->ev_used) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
@@ -727,7 +814,9 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
   if ((st0 = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return fail(st0);
   PP_CREATE_HIP(ppk::launch_qprep(c->dbunch, c->bid, n_total, S.q, c->mixed() ? c->plane(6) : nullptr, c->qt64,
                                   c->stream));
-  c->tun = default_tuning(c->mixed());
+  int64_t min_n = INT64_MAX;
+  for (int b = 0; b < n_bunches; ++b) min_n = std::min<int64_t>(min_n, bunches[b].n);
+  c->tun = default_tuning(c->mixed(), min_n);
   pp_status st = build_items(c);
   if (st != PP_OK) return fail(st);
 #undef PP_CREATE_HIP

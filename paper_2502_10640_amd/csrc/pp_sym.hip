@@ -1,0 +1,285 @@
+// pp_sym.hip -- symmetric mixed-precision pair sum for gfx950.
+//
+// Coulomb's law Eq. (A) is antisymmetric in i and j (Sec. 2.1): the pair term
+// q_j d / (|d|^2 + eps^2)^(3/2) added to E_i reappears, with q_i in place of
+// q_j and the opposite sign, in E_j.  One v_rsq_f32 therefore serves two
+// ordered interactions.  On gfx950 the reciprocal square root costs 10-12
+// FP32 issue slots inside a pair evaluation, so this halves the dominant cost.
+//
+// An item pairs receiver block I (held in VGPRs, i_per_lane per lane, 8 waves)
+// with source block J, swept in groups of 64 sources staged in LDS.  In step s
+// of a group, lane l meets source (l + s) mod 64 (every lane reads a distinct
+// LDS address).  The source-side partial of that source travels with it: after
+// each step every lane takes over the partial of its upper neighbour
+// (ds_bpermute, an explicit cross-lane move).  Every 16 steps the partials are
+// handed to their sources' home lanes (lane l owns source l) and added there
+// with two-sum.  After the group the 8 waves' pairs are combined in wave order
+// and added (two-sum) to the block's source-side accumulator in HBM.  The receiver side is a plain FP32 sum over
+// each group of 64 sources, two-summed into registers, and added to the
+// receiver-side accumulator at the end of the item.
+//
+// Diagonal items (I == J) evaluate the ordered pairs inside one block with the
+// self term masked, write the receiver-side accumulator and clear the
+// source-side one; they run first.  Rounds of off-diagonal items follow, one
+// launch per round; within a round no two items touch the same accumulator,
+// and the order of rounds fixes the order of every addition.
+#include "pp_device.h"
+#include "pp_internal.h"
+
+#include <cmath>
+
+namespace ppk {
+namespace {
+
+// Out-of-range particles of a ragged block sit here: any separation to a real
+// particle squares to +inf in FP32, rsq(+inf) = 0, so their terms are exact
+// zeros in both directions.
+constexpr float SENTINEL = 1.5e19f;
+
+__device__ __forceinline__ float lane_read(float v, int src_lane) {
+  // value of v in lane src_lane of this wavefront (ds_bpermute: LDS crossbar, no LDS memory)
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+
+template <int K, bool UQ, bool PHI, bool DIAG>
+__device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, const float4* __restrict__ sjl, int l,
+                                            int gsel, const float (&xh)[K], const float (&yh)[K],
+                                            const float (&zh)[K], const float (&xl)[K], const float (&yl)[K],
+                                            const float (&zl)[K], const float (&qi)[K], float eps2,
+                                            float (&ti)[3][K], float (&tip)[K], float (&Sj)[4], float (&Cj)[4]) {
+  // aj: plain partial of the source met in this step, (l + s) mod 64; it moves
+  // one lane down every step so that it stays with its source.
+  float aj[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < 64; ++s) {
+    const int jj = (l + s) & 63;
+    const float4 h = sjh[jj];
+    const float4 lo = sjl[jj];
+    float dx[K], dy[K], dz[K], r2[K], inv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      dx[k] = (xh[k] - h.x) + (xl[k] - lo.x);
+      dy[k] = (yh[k] - h.y) + (yl[k] - lo.y);
+      dz[k] = (zh[k] - h.z) + (zl[k] - lo.z);
+      r2[k] = fmaf(dz[k], dz[k], fmaf(dy[k], dy[k], fmaf(dx[k], dx[k], eps2)));
+      if (DIAG) {
+        // self term: receiver group gsel + k, source lane jj == l at s == 0
+        if (s == 0 && gsel == k) r2[k] = __builtin_inff();
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) inv[k] = __builtin_amdgcn_rsqf(r2[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float s3 = (inv[k] * inv[k]) * inv[k];
+      const float fi = UQ ? s3 : h.w * s3;
+      ti[0][k] = fmaf(dx[k], fi, ti[0][k]);
+      ti[1][k] = fmaf(dy[k], fi, ti[1][k]);
+      ti[2][k] = fmaf(dz[k], fi, ti[2][k]);
+      if (PHI) tip[k] += UQ ? inv[k] : h.w * inv[k];
+      if (!DIAG) {
+        const float fj = UQ ? s3 : qi[k] * s3;
+        aj[0] = fmaf(-dx[k], fj, aj[0]);
+        aj[1] = fmaf(-dy[k], fj, aj[1]);
+        aj[2] = fmaf(-dz[k], fj, aj[2]);
+        if (PHI) aj[3] += UQ ? inv[k] : qi[k] * inv[k];
+      }
+    }
+    if (!DIAG) {
+      if ((s & 15) == 15) {
+        // hand each partial to its source's home lane: lane l receives the
+        // partial of source l from lane (l - s) mod 64, adds it with two-sum
+#pragma unroll
+        for (int q = 0; q < (PHI ? 4 : 3); ++q) {
+          const float m = lane_read(aj[q], (l - s) & 63);
+          two_sum(Sj[q], Cj[q], m);
+          aj[q] = 0.f;
+        }
+      } else {
+        // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
+#pragma unroll
+        for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read(aj[q], (l + 1) & 63);
+      }
+    }
+  }
+}
+
+struct SymShared {
+  float4 sjh[64];                // source group: hi position, normalised charge
+  float4 sjl[64];                // source group: lo position
+  float xw[SYM_WAVES][8][64];    // per-wave two-sum pairs for the cross-wave combine
+};
+
+template <int K, bool UQ, bool PHI, bool DIAG>
+__device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
+  float4* sjh = sh.sjh;
+  float4* sjl = sh.sjl;
+  auto& xw = sh.xw;
+
+  const BunchDev& B = a.bunches[it.b];
+  const int n = (int)B.n;
+  const int64_t off = B.off;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  constexpr int BS = SYM_WAVES * 64 * K;
+  const int ibase = it.I * BS, jbase0 = it.J * BS;
+  const float eps2 = B.eps2s;
+
+  float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], qi[K];
+  float Si[3][K], Ci[3][K], Sip[K], Cip[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int li = ibase + (w * K + k) * 64 + l;
+    if (li < n) {
+      const int64_t g = off + li;
+      xh[k] = a.xh[g]; yh[k] = a.yh[g]; zh[k] = a.zh[g];
+      xl[k] = a.xl[g]; yl[k] = a.yl[g]; zl[k] = a.zl[g];
+      qi[k] = UQ ? 1.f : a.qt[g];
+    } else {
+      xh[k] = yh[k] = zh[k] = SENTINEL;
+      xl[k] = yl[k] = zl[k] = 0.f;
+      qi[k] = 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Si[c][k] = Ci[c][k] = 0.f;
+    Sip[k] = Cip[k] = 0.f;
+  }
+
+  for (int g = 0; g < BS / 64; ++g) {
+    const int jg = jbase0 + g * 64;
+    __syncthreads();  // LDS of the previous group is free
+    if (w == 0) {
+      const int lj = jg + l;
+      if (lj < n) {
+        const int64_t gi = off + lj;
+        sjh[l] = make_float4(a.xh[gi], a.yh[gi], a.zh[gi], UQ ? 1.f : a.qt[gi]);
+        sjl[l] = make_float4(a.xl[gi], a.yl[gi], a.zl[gi], 0.f);
+      } else {
+        sjh[l] = make_float4(SENTINEL, SENTINEL, SENTINEL, 0.f);
+        sjl[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+
+    float ti[3][K], tip[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.f; }
+    float Sj[4] = {0.f, 0.f, 0.f, 0.f}, Cj[4] = {0.f, 0.f, 0.f, 0.f};
+    // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
+    sweep_group<K, UQ, PHI, DIAG>(sjh, sjl, l, DIAG ? g - w * K : -1, xh, yh, zh, xl, yl, zl, qi, eps2, ti,
+                                  tip, Sj, Cj);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      two_sum(Si[0][k], Ci[0][k], ti[0][k]);
+      two_sum(Si[1][k], Ci[1][k], ti[1][k]);
+      two_sum(Si[2][k], Ci[2][k], ti[2][k]);
+      if (PHI) two_sum(Sip[k], Cip[k], tip[k]);
+    }
+    if (!DIAG) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xw[w][q][l] = Sj[q];
+        xw[w][4 + q][l] = Cj[q];
+      }
+      __syncthreads();
+      if (w == 0) {
+        float S[4], C[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { S[q] = xw[0][q][l]; C[q] = xw[0][4 + q][l]; }
+        for (int ww = 1; ww < SYM_WAVES; ++ww) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) two_sum_pair(S[q], C[q], xw[ww][q][l], xw[ww][4 + q][l]);
+        }
+        const int lj = jg + l;
+        if (lj < n) {
+          const int64_t slot = off + lj;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            float gs = a.acc[(6 + c) * a.P + slot], gc = a.acc[(9 + c) * a.P + slot];
+            two_sum_pair(gs, gc, S[c], C[c]);
+            a.acc[(6 + c) * a.P + slot] = gs;
+            a.acc[(9 + c) * a.P + slot] = gc;
+          }
+          if (PHI) {
+            float gs = a.acc[14 * a.P + slot], gc = a.acc[15 * a.P + slot];
+            two_sum_pair(gs, gc, S[3], C[3]);
+            a.acc[14 * a.P + slot] = gs;
+            a.acc[15 * a.P + slot] = gc;
+          }
+        }
+      }
+    }
+  }
+
+  // receiver side
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int li = ibase + (w * K + k) * 64 + l;
+    if (li >= n) continue;
+    const int64_t slot = off + li;
+    if (DIAG) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a.acc[c * a.P + slot] = Si[c][k];
+        a.acc[(3 + c) * a.P + slot] = Ci[c][k];
+        a.acc[(6 + c) * a.P + slot] = 0.f;
+        a.acc[(9 + c) * a.P + slot] = 0.f;
+      }
+      if (PHI) {
+        a.acc[12 * a.P + slot] = Sip[k];
+        a.acc[13 * a.P + slot] = Cip[k];
+        a.acc[14 * a.P + slot] = 0.f;
+        a.acc[15 * a.P + slot] = 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float gs = a.acc[c * a.P + slot], gc = a.acc[(3 + c) * a.P + slot];
+        two_sum_pair(gs, gc, Si[c][k], Ci[c][k]);
+        a.acc[c * a.P + slot] = gs;
+        a.acc[(3 + c) * a.P + slot] = gc;
+      }
+      if (PHI) {
+        float gs = a.acc[12 * a.P + slot], gc = a.acc[13 * a.P + slot];
+        two_sum_pair(gs, gc, Sip[k], Cip[k]);
+        a.acc[12 * a.P + slot] = gs;
+        a.acc[13 * a.P + slot] = gc;
+      }
+    }
+  }
+}
+
+template <int K, bool UQ, bool PHI>
+__global__ __launch_bounds__(SYM_WG) void pair_sym_kernel(SymArgs a, int32_t first) {
+  __shared__ SymShared sh;
+  const SymItem it = a.items[first + blockIdx.x];
+  if (it.diag)
+    sym_item<K, UQ, PHI, true>(a, it, sh);
+  else
+    sym_item<K, UQ, PHI, false>(a, it, sh);
+}
+
+template <int K, bool UQ, bool PHI>
+hipError_t go_sym(const SymArgs& a, int32_t first, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL((pair_sym_kernel<K, UQ, PHI>), dim3(count), dim3(SYM_WG), 0, s, a, first);
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t go_sym_k(const SymArgs& a, int32_t first, int32_t count, bool uq, bool phi, hipStream_t s) {
+  if (uq) return phi ? go_sym<K, true, true>(a, first, count, s) : go_sym<K, true, false>(a, first, count, s);
+  return phi ? go_sym<K, false, true>(a, first, count, s) : go_sym<K, false, false>(a, first, count, s);
+}
+
+}  // namespace
+
+hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
+                      hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (i_per_lane) {
+    case 1: return go_sym_k<1>(a, first, count, uniform_q, with_phi, s);
+    case 2: return go_sym_k<2>(a, first, count, uniform_q, with_phi, s);
+    case 4: return go_sym_k<4>(a, first, count, uniform_q, with_phi, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ppk

@@ -327,3 +327,58 @@ def test_full_size_sampled_parity_cold_sphere_1m(orc):
         got = gpu_field(sim, sl=recv)
     ref = oracle_field(orc, b, recv=recv)
     check_field(got, ref, TOL["mixed"], "cold_sphere_1m/mixed sampled")
+
+
+# ---------------------------------------------------------------------------
+# symmetric (one rsq per unordered pair) schedule
+# ---------------------------------------------------------------------------
+
+def _sym_bunches():
+    return [wl.workload("gaussian_65536", n_override=3000)[0], wl.workload("cold_sphere_2048")[0],
+            mixed_charge_bunch(1500, seed=5), wl.workload("cold_sphere_2048", n_override=5)[0]]
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_symmetric_field_parity(orc, K):
+    bunches = _sym_bunches()
+    say(f"symmetric field K={K} sizes={[b.n for b in bunches]}")
+    with Sim(bunches, "mixed", tuning={"symmetric": 1, "i_per_lane": K}) as sim:
+        assert sim.tuning()["symmetric"] == 1
+        full = gpu_field(sim)
+        for k, b in enumerate(bunches):
+            sl = sim.bunch_slice(k)
+            got = {key: v[sl] for key, v in full.items()}
+            check_field(got, oracle_field(orc, b), TOL["mixed"], f"sym K={K} n={b.n}")
+
+
+def test_symmetric_push_graph_and_trajectory(orc):
+    b = wl.workload("gaussian_65536", n_override=2500)[0]
+    say("symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps")
+    tun = {"symmetric": 1, "i_per_lane": 1, "graph_steps": 3}
+    res = []
+    for mode in ("push", "graph"):
+        with Sim([b], "mixed", tuning=tun) as sim:
+            if mode == "push":
+                sim.push(8)
+            else:
+                sim.step_batched(8, graph=True)
+            res.append({k: sim.host(k) for k in ("x", "y", "z", "vx", "vy", "vz")})
+    for k in res[0]:
+        np.testing.assert_array_equal(res[0][k], res[1][k])
+    s = _state(b)
+    orc.vv(s, 8)
+    v_rms = math.sqrt(np.mean(s.vx ** 2 + s.vy ** 2 + s.vz ** 2))
+    ev = max(np.abs(res[0][k] - getattr(s, k)).max() for k in ("vx", "vy", "vz")) / v_rms
+    print(f"    symmetric trajectory: max|dv|/v_rms={ev:.3e}", flush=True)
+    assert ev <= 1e-6
+
+
+def test_symmetric_equals_itself_run_to_run():
+    b = wl.workload("cold_sphere_2048")[0]
+    say("symmetric run-to-run bitwise")
+    outs = []
+    for _ in range(2):
+        with Sim([b], "mixed", tuning={"symmetric": 1, "i_per_lane": 2}) as sim:
+            outs.append(gpu_field(sim))
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
