@@ -180,30 +180,20 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
         xw[w][4 + q][l] = Cj[q];
       }
       __syncthreads();
-      if (w == 0) {
-        float S[4], C[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { S[q] = xw[0][q][l]; C[q] = xw[0][4 + q][l]; }
-        for (int ww = 1; ww < SYM_WAVES; ++ww) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) two_sum_pair(S[q], C[q], xw[ww][q][l], xw[ww][4 + q][l]);
-        }
+      // one thread per (source, component): waves 0-3 combine the 8 waves'
+      // pairs in wave order and add them to the source-side accumulator
+      const int q = tid >> 6;  // 0..2 field components, 3 potential
+      if (q < (PHI ? 4 : 3)) {
+        float S = xw[0][q][l], C = xw[0][4 + q][l];
+        for (int ww = 1; ww < SYM_WAVES; ++ww) two_sum_pair(S, C, xw[ww][q][l], xw[ww][4 + q][l]);
         const int lj = jg + l;
         if (lj < n) {
           const int64_t slot = off + lj;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            float gs = a.acc[(6 + c) * a.P + slot], gc = a.acc[(9 + c) * a.P + slot];
-            two_sum_pair(gs, gc, S[c], C[c]);
-            a.acc[(6 + c) * a.P + slot] = gs;
-            a.acc[(9 + c) * a.P + slot] = gc;
-          }
-          if (PHI) {
-            float gs = a.acc[14 * a.P + slot], gc = a.acc[15 * a.P + slot];
-            two_sum_pair(gs, gc, S[3], C[3]);
-            a.acc[14 * a.P + slot] = gs;
-            a.acc[15 * a.P + slot] = gc;
-          }
+          const int ps = q < 3 ? 6 + q : 14, pc = q < 3 ? 9 + q : 15;
+          float gs = a.acc[ps * a.P + slot], gc = a.acc[pc * a.P + slot];
+          two_sum_pair(gs, gc, S, C);
+          a.acc[ps * a.P + slot] = gs;
+          a.acc[pc * a.P + slot] = gc;
         }
       }
     }
