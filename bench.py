@@ -58,6 +58,11 @@ def parse():
     p.add_argument("--tuning", default="", help="k=v,... tiling override (i_per_lane, sum_tile, ...)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    p.add_argument("--mode", default="throughput", choices=["throughput", "drift"],
+                   help="drift: run --steps steps in mixed and FP64 precision and report the total-energy drift "
+                        "and the mixed-vs-FP64 energy gap every --every steps (no timing line)")
+    p.add_argument("--every", type=int, default=20)
+    p.add_argument("--precisions", default="mixed,fp64")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
                    help="only run a plain device-to-device copy of this many MiB (3 times) and exit: the "
                         "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -100,8 +105,66 @@ def cpu_baseline(bunches, target_s):
                       f"evaluation with compensated sums ({pairs:.3e} pairs in {dt:.2f} s)"}
 
 
+def total_energy(sim):
+    """Total energy per bunch: kinetic from the state, potential from the GPU's
+    softened potential (pp_field with phi); the sums are done here in FP64."""
+    import numpy as np
+    f = sim.field(want_phi=True)
+    phi = f["phi"].cpu().numpy()
+    v2 = sim.host("vx") ** 2 + sim.host("vy") ** 2 + sim.host("vz") ** 2
+    q, m = sim.host("q"), sim.host("m")
+    out = []
+    for k, b in enumerate(sim.bunches):
+        sl = sim.bunch_slice(k)
+        out.append(0.5 * b.weight * float(np.sum(m[sl] * v2[sl])) + 0.5 * b.weight * float(np.sum(q[sl] * phi[sl])))
+    return out
+
+
+def drift(a):
+    import numpy as np
+    import torch
+    from paper_2502_10640_amd import workloads as wl
+    from paper_2502_10640_amd.sim import Simulation
+    bunches = wl.workload(a.workload, n_override=a.n or None)
+    traj = {}
+    wall = {}
+    for prec in a.precisions.split(","):
+        print(f"[drift] {a.workload} {prec} {a.steps} steps", file=sys.stderr, flush=True)
+        with Simulation(bunches, prec) as sim:
+            es = [total_energy(sim)]
+            t_run = 0.0
+            done = 0
+            while done < a.steps:
+                k = min(a.every, a.steps - done)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step_batched(k, graph=False)
+                torch.cuda.synchronize()
+                t_run += time.perf_counter() - t0
+                done += k
+                es.append(total_energy(sim))
+                print(f"[drift] {prec} step {done}", file=sys.stderr, flush=True)
+            traj[prec] = np.array(es)
+            wall[prec] = t_run
+    pairs = float(sum(b.n * (b.n - 1) for b in bunches))
+    out = {"mode": "drift", "workload": a.workload, "n_particles": sum(b.n for b in bunches), "steps": a.steps,
+           "every": a.every, "dt_omega": [b.meta.get("dt_omega") for b in bunches][:4]}
+    for prec, e in traj.items():
+        e0 = np.abs(e[0])
+        out[f"max_rel_drift_{prec}"] = float(np.max(np.abs(e - e[0]) / e0))
+        out[f"final_rel_drift_{prec}"] = float(np.max(np.abs(e[-1] - e[0]) / e0))
+        out[f"pairs_per_s_{prec}"] = a.steps * pairs / wall[prec]
+    if "mixed" in traj and "fp64" in traj:
+        gap = np.abs(traj["mixed"] - traj["fp64"]) / np.abs(traj["fp64"][0])
+        out["max_rel_gap_mixed_vs_fp64"] = float(np.max(gap))
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
+    if a.mode == "drift":
+        drift(a)
+        return
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)
         return
