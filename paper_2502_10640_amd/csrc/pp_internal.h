@@ -35,6 +35,9 @@ struct BunchDev {
   int32_t n_chunks;   // j-chunks the bunch's sources are split into
   int64_t chunk_len;  // sources per chunk (multiple of JT but the last)
   int64_t pbase;      // first partial-sum slot of the bunch
+  int64_t cstart;     // spatial sort: first position of the bunch in the compacted key array
+  int32_t gbase;      // spatial sort: first 64-particle group box of the bunch
+  int32_t bbase;      // spatial sort: first symmetric-block box of the bunch
 };
 
 // One unit of pair work: receivers [i0, i0 + i_per_lane * WG) of bunch b
@@ -93,6 +96,33 @@ struct SymArgs {
   const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;
   float* acc;   // SYM_PLANES planes of length P, indexed by particle
   int64_t P;
+  // near/far split (needs the spatial sort): a source group whose box is
+  // farther than near_frac * U from the receiver block's box uses plain FP32
+  // separations; near_frac = 0 keeps hi/lo separations everywhere
+  float near_frac;
+  const float* gbox;       // [group][6]: min xyz, max xyz of the FP32 high parts
+  const float* bbox;       // [block][6]
+  const uint32_t* ubits;   // per-bunch bound U on |scaled coordinate| (float bits)
+};
+
+// Spatial sort (pp_sort.hip): keys per tile of the radix sort.
+constexpr int SORT_TILE = 2048;
+
+struct SortArgs {
+  const BunchDev* bunches;
+  int32_t nb;
+  const int32_t* bid;
+  int64_t n_total;
+  int64_t n_in;            // particles inside bunches
+  const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;    // mirror, particle order
+  float *sxh, *syh, *szh, *sxl, *syl, *szl, *sqt;   // mirror, sorted order
+  uint32_t* ubits;
+  uint64_t *keys, *keys2;
+  int32_t *vals, *vals2;
+  uint32_t* hist;
+  int32_t* rank;           // sorted position of each particle
+  float* gbox;
+  float* bbox;
 };
 
 struct PackArgs {
@@ -125,6 +155,7 @@ struct FinalArgs {
   double *ax, *ay, *az;
   double *ex, *ey, *ez, *phi;   // FIN_FIELD outputs (phi may be null)
   int32_t sym;                  // partials are the symmetric accumulators
+  const int32_t* rank;          // symmetric accumulators in sorted order: slot = rank[i]
 };
 
 // Diagnostics: per-bunch reduction record in device memory (doubles).
@@ -163,6 +194,8 @@ hipError_t launch_pair(const PairArgs& a, bool mixed, int i_per_lane, int sum_ti
 hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s);
 hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
                       hipStream_t s);
+hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
+                       int32_t groups_per_block, hipStream_t s);
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,
                         float* qt, double* qt64, hipStream_t s);
 hipError_t launch_minmax(const BunchDev* bunches, int32_t n_bunches, const double* x, const double* y,

@@ -346,10 +346,11 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
     // receiver side (S, C) then source side (S, C), in that order
     const float* f = a.pf;
     const int64_t P = a.P;
-    ex = ((double)f[0 * P + i] + (double)f[3 * P + i]) + ((double)f[6 * P + i] + (double)f[9 * P + i]);
-    ey = ((double)f[1 * P + i] + (double)f[4 * P + i]) + ((double)f[7 * P + i] + (double)f[10 * P + i]);
-    ez = ((double)f[2 * P + i] + (double)f[5 * P + i]) + ((double)f[8 * P + i] + (double)f[11 * P + i]);
-    if (want_phi) ph = ((double)f[12 * P + i] + (double)f[13 * P + i]) + ((double)f[14 * P + i] + (double)f[15 * P + i]);
+    const int64_t r = a.rank ? (int64_t)a.rank[i] : i;  // accumulator slot (sorted order)
+    ex = ((double)f[0 * P + r] + (double)f[3 * P + r]) + ((double)f[6 * P + r] + (double)f[9 * P + r]);
+    ey = ((double)f[1 * P + r] + (double)f[4 * P + r]) + ((double)f[7 * P + r] + (double)f[10 * P + r]);
+    ez = ((double)f[2 * P + r] + (double)f[5 * P + r]) + ((double)f[8 * P + r] + (double)f[11 * P + r]);
+    if (want_phi) ph = ((double)f[12 * P + r] + (double)f[13 * P + r]) + ((double)f[14 * P + r] + (double)f[15 * P + r]);
   }
   for (int c = 0; c < ((MIXED && a.sym) ? 0 : B.n_chunks); ++c) {
     const int64_t s = B.pbase + (int64_t)c * B.n + li;

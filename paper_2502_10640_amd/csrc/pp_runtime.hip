@@ -73,6 +73,17 @@ struct pp_ctx {
   size_t sitems_cap = 0;
   std::vector<std::pair<int32_t, int32_t>> launches;  // (first item, items) per launch
   float* acc = nullptr;            // symmetric accumulators, SYM_PLANES x n_total
+  // spatial sort of the near/far split (allocated on first use)
+  float* smir = nullptr;           // 7 planes in sorted order
+  uint64_t* keys = nullptr;        // 2 x n_in (ping-pong)
+  int32_t* vals = nullptr;         // 2 x n_in
+  uint32_t* hist = nullptr;        // 256 x sort tiles
+  int32_t* rank = nullptr;         // sorted slot of each particle
+  uint32_t* ubits = nullptr;       // per-bunch coordinate bound
+  float* gbox = nullptr;           // 6 x 64-particle groups
+  float* bbox = nullptr;           // 6 x symmetric blocks (sized for i_per_lane 1)
+  int64_t n_in = 0;                // particles inside bunches
+  int32_t n_groups = 0, n_blocks = 0, n_blocks_max = 0;
   void* hpin = nullptr;        // pinned host staging for every host<->device copy
   size_t hpin_bytes = 0;
 
@@ -95,6 +106,7 @@ struct pp_ctx {
   float* plane(int k) const { return mir + (size_t)k * (size_t)n_total; }
   bool mixed() const { return prec == PP_MIXED; }
   bool sym() const { return prec == PP_MIXED && tun.symmetric != 0; }
+  bool far() const { return sym() && tun.far_split > 0; }
   int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
 };
 
@@ -207,6 +219,20 @@ pp_status build_sym(pp_ctx* c) {
     c->sitems_cap = items.size();
   }
   if (!c->acc) PP_HIP(c, dalloc(&c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total));
+  if (c->far() && !c->smir) {
+    // host-side shape checks of what the sort kernels assume
+    if (c->n_total > INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "far split: more than 2^31 - 1 particles");
+    const size_t n = (size_t)c->n_total, nin = (size_t)c->n_in;
+    const size_t tiles = (nin + ppk::SORT_TILE - 1) / ppk::SORT_TILE;
+    PP_HIP(c, dalloc(&c->smir, 7 * n));
+    PP_HIP(c, dalloc(&c->keys, 2 * nin));
+    PP_HIP(c, dalloc(&c->vals, 2 * nin));
+    PP_HIP(c, dalloc(&c->hist, 256 * tiles));
+    PP_HIP(c, dalloc(&c->rank, n));
+    PP_HIP(c, dalloc(&c->ubits, (size_t)c->nb));
+    PP_HIP(c, dalloc(&c->gbox, 6 * (size_t)c->n_groups));
+    PP_HIP(c, dalloc(&c->bbox, 6 * (size_t)c->n_blocks_max));
+  }
   return h2d(c, c->sitems, items.data(), items.size() * sizeof(ppk::SymItem));
 }
 
@@ -223,6 +249,7 @@ pp_status build_items(pp_ctx* c) {
   struct Cand { WorkItem w; double cost; };
   std::vector<Cand> cand;
   int64_t pbase = 0;
+  int64_t cbase = 0, gbase = 0, bbase = 0, bmax = 0;
   for (int b = 0; b < c->nb; ++b) {
     const int64_t n = c->hb[b].n;
     const double full = (double)std::min(BI, n) * (double)n;
@@ -237,6 +264,17 @@ pp_status build_items(pp_ctx* c) {
     B.chunk_len = chunk_len;
     B.pbase = pbase;
     pbase += nch * n;
+    // spatial-sort bases: compacted keys, 64-particle groups, symmetric blocks
+    const int64_t bs = (int64_t)ppk::SYM_WG * c->tun.i_per_lane;
+    if (cbase + n > INT32_MAX || gbase + (n + 63) / 64 > INT32_MAX)
+      return set_err(c, PP_ERR_INVALID_ARG, "work list: more than 2^31 - 1 particles in bunches");
+    B.cstart = cbase;
+    B.gbase = (int32_t)gbase;
+    B.bbase = (int32_t)bbase;
+    cbase += n;
+    gbase += (n + 63) / 64;
+    bbase += (n + bs - 1) / bs;
+    bmax += (n + ppk::SYM_WG - 1) / ppk::SYM_WG;
     const int64_t nib = (n + BI - 1) / BI;
     for (int64_t ib = 0; ib < nib; ++ib) {
       for (int64_t ch = 0; ch < nch; ++ch) {
@@ -249,6 +287,10 @@ pp_status build_items(pp_ctx* c) {
       }
     }
   }
+  c->n_in = cbase;
+  c->n_groups = (int32_t)gbase;
+  c->n_blocks = (int32_t)bbase;
+  c->n_blocks_max = (int32_t)bmax;
   std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) { return x.cost > y.cost; });
   if (cand.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "work list too long");
   std::vector<WorkItem> items(cand.size());
@@ -327,6 +369,7 @@ ppk::FinalArgs final_args(pp_ctx* c) {
   a.pd = (const double*)c->part;
   a.P = c->sym() ? c->n_total : c->P;
   a.sym = c->sym() ? 1 : 0;
+  a.rank = c->far() ? c->rank : nullptr;
   a.q = c->st.q;
   a.m = c->st.m;
   a.vx = c->st.vx; a.vy = c->st.vy; a.vz = c->st.vz;
@@ -373,6 +416,39 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
     sa.qt = c->plane(6);
     sa.acc = c->acc;
     sa.P = c->n_total;
+    if (c->far()) {
+      ppk::SortArgs so{};
+      so.bunches = c->dbunch;
+      so.nb = c->nb;
+      so.bid = c->bid;
+      so.n_total = c->n_total;
+      so.n_in = c->n_in;
+      so.xh = c->plane(0); so.yh = c->plane(1); so.zh = c->plane(2);
+      so.xl = c->plane(3); so.yl = c->plane(4); so.zl = c->plane(5);
+      so.qt = c->plane(6);
+      float* sp[7];
+      for (int k = 0; k < 7; ++k) sp[k] = c->smir + (size_t)k * (size_t)c->n_total;
+      so.sxh = sp[0]; so.syh = sp[1]; so.szh = sp[2];
+      so.sxl = sp[3]; so.syl = sp[4]; so.szl = sp[5];
+      so.sqt = sp[6];
+      so.ubits = c->ubits;
+      so.keys = c->keys; so.keys2 = c->keys + c->n_in;
+      so.vals = c->vals; so.vals2 = c->vals + c->n_in;
+      so.hist = c->hist;
+      so.rank = c->rank;
+      so.gbox = c->gbox;
+      so.bbox = c->bbox;
+      int bunch_bits = 0;
+      while ((int64_t(1) << bunch_bits) < c->nb) ++bunch_bits;
+      PP_HIP(c, ppk::launch_sort(so, 30 + bunch_bits, c->n_groups, c->n_blocks, 8 * c->tun.i_per_lane, s));
+      sa.xh = sp[0]; sa.yh = sp[1]; sa.zh = sp[2];
+      sa.xl = sp[3]; sa.yl = sp[4]; sa.zl = sp[5];
+      sa.qt = sp[6];
+      sa.near_frac = std::ldexp(1.0f, -c->tun.far_split);
+      sa.gbox = c->gbox;
+      sa.bbox = c->bbox;
+      sa.ubits = c->ubits;
+    }
     for (const auto& L : c->launches)
       PP_HIP(c, ppk::launch_sym(sa, L.first, L.second, c->tun.i_per_lane, c->uniform_q, phi, s));
   } else {
@@ -457,6 +533,7 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
   if (t.symmetric != 0 && t.symmetric != 1) return false;
   if (t.symmetric && (!mixed || k == 8)) return false;
+  if (t.far_split < 0 || t.far_split > 8 || (t.far_split > 0 && !t.symmetric)) return false;
   return true;
 }
 
@@ -500,7 +577,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v2";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v3";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -519,7 +596,7 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
   pp_tuning v{};
   bool found = false;
   while (f >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
-         v.symmetric) {
+         v.symmetric >> v.far_split) {
     if (k == key) { *t = v; found = true; }
   }
   return found;
@@ -536,7 +613,7 @@ void tune_store(const std::string& key, const pp_tuning& t) {
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
-      << t.graph_steps << " " << t.symmetric << "\n";
+      << t.graph_steps << " " << t.symmetric << " " << t.far_split << "\n";
 }
 
 pp_status time_eval(pp_ctx* c, int reps, double* ms) {
@@ -629,6 +706,14 @@ pp_status autotune(pp_ctx* c) {
         pp_tuning t = best;
         t.symmetric = sym;
         t.i_per_lane = k;
+        t.far_split = sym ? t.far_split : 0;
+        if ((s = trial(t)) != PP_OK) return s;
+      }
+    }
+    if (best.symmetric) {
+      for (int f : {0, 2, 3, 4}) {
+        pp_tuning t = best;
+        t.far_split = f;
         if ((s = trial(t)) != PP_OK) return s;
       }
     }
@@ -643,7 +728,8 @@ void free_all(pp_ctx* c) {
   drop_graph(c);
   auto f = [](void* p) { if (p) hipFree(p); };
   f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
-  f(c->items); f(c->sitems); f(c->acc); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
+  f(c->items); f(c->sitems); f(c->acc);
+  f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->bbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
   if (c->hpin) hipHostFree(c->hpin);
   for (auto& e : c->ev_pool) hipEventDestroy(e);
   for (auto& p : c->ev_used) { hipEventDestroy(p.first); hipEventDestroy(p.second); }

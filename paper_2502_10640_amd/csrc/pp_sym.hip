@@ -41,7 +41,7 @@ __device__ __forceinline__ float lane_read(float v, int src_lane) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
 }
 
-template <int K, bool UQ, bool PHI, bool DIAG>
+template <int K, bool UQ, bool PHI, bool DIAG, bool FAR>
 __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, const float4* __restrict__ sjl, int l,
                                             int gsel, const float (&xh)[K], const float (&yh)[K],
                                             const float (&zh)[K], const float (&xl)[K], const float (&yl)[K],
@@ -53,13 +53,26 @@ __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, cons
   for (int s = 0; s < 64; ++s) {
     const int jj = (l + s) & 63;
     const float4 h = sjh[jj];
-    const float4 lo = sjl[jj];
     float dx[K], dy[K], dz[K], r2[K], inv[K];
+    if (FAR) {
+      // far group: plain FP32 separations of the high parts
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dx[k] = xh[k] - h.x;
+        dy[k] = yh[k] - h.y;
+        dz[k] = zh[k] - h.z;
+      }
+    } else {
+      const float4 lo = sjl[jj];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dx[k] = (xh[k] - h.x) + (xl[k] - lo.x);
+        dy[k] = (yh[k] - h.y) + (yl[k] - lo.y);
+        dz[k] = (zh[k] - h.z) + (zl[k] - lo.z);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      dx[k] = (xh[k] - h.x) + (xl[k] - lo.x);
-      dy[k] = (yh[k] - h.y) + (yl[k] - lo.y);
-      dz[k] = (zh[k] - h.z) + (zl[k] - lo.z);
       r2[k] = fmaf(dz[k], dz[k], fmaf(dy[k], dy[k], fmaf(dx[k], dx[k], eps2)));
       if (DIAG) {
         // self term: receiver group gsel + k, source lane jj == l at s == 0
@@ -123,6 +136,18 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
   const int ibase = it.I * BS, jbase0 = it.J * BS;
   const float eps2 = B.eps2s;
 
+  // near/far split: receiver block box and threshold (uniform over the item)
+  const bool split = !DIAG && a.near_frac > 0.f;
+  float ib[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float dfar2 = 0.f;
+  if (split) {
+    const float* bx = a.bbox + (int64_t)(B.bbase + it.I) * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ib[c] = bx[c];
+    const float dfar = a.near_frac * __uint_as_float(a.ubits[it.b]);
+    dfar2 = dfar * dfar;
+  }
+
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], qi[K];
   float Si[3][K], Ci[3][K], Sip[K], Cip[K];
 #pragma unroll
@@ -163,9 +188,27 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
 #pragma unroll
     for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.f; }
     float Sj[4] = {0.f, 0.f, 0.f, 0.f}, Cj[4] = {0.f, 0.f, 0.f, 0.f};
+    bool far = false;
+    if (split) {
+      if (jg >= n) {
+        far = true;  // sentinel-only group: every term is an exact zero on either path
+      } else {
+        const float* gb = a.gbox + (int64_t)(B.gbase + jg / 64) * 6;
+        float gap2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float d = fmaxf(0.f, fmaxf(gb[c] - ib[3 + c], ib[c] - gb[3 + c]));
+          gap2 = fmaf(d, d, gap2);
+        }
+        far = gap2 > dfar2;
+      }
+    }
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
-    sweep_group<K, UQ, PHI, DIAG>(sjh, sjl, l, DIAG ? g - w * K : -1, xh, yh, zh, xl, yl, zl, qi, eps2, ti,
-                                  tip, Sj, Cj);
+    if (far)
+      sweep_group<K, UQ, PHI, DIAG, true>(sjh, sjl, l, -1, xh, yh, zh, xl, yl, zl, qi, eps2, ti, tip, Sj, Cj);
+    else
+      sweep_group<K, UQ, PHI, DIAG, false>(sjh, sjl, l, DIAG ? g - w * K : -1, xh, yh, zh, xl, yl, zl, qi, eps2,
+                                           ti, tip, Sj, Cj);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       two_sum(Si[0][k], Ci[0][k], ti[0][k]);

@@ -71,7 +71,8 @@ class Diag(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("i_per_lane", ctypes.c_int32), ("sum_tile", ctypes.c_int32), ("chunk_pairs_log2", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("symmetric", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("symmetric", ctypes.c_int32),
+                ("far_split", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +84,7 @@ class Profile(ctypes.Structure):
 
 _LIB = None
 _VP = ctypes.c_void_p
+ABI_VERSION = 2  # PP_ABI_VERSION of include/pp.h
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -117,6 +119,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
+    if L.pp_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {L.pp_abi_version()}, this binding expects {ABI_VERSION}: "
+                           "rebuild it with __graft_entry__.build()")
     _LIB = L
     return L
 

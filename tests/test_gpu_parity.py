@@ -382,3 +382,86 @@ def test_symmetric_equals_itself_run_to_run():
             outs.append(gpu_field(sim))
     for k in outs[0]:
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+# ---------------------------------------------------------------------------
+# near/far split of the symmetric schedule (spatial sort every evaluation)
+# ---------------------------------------------------------------------------
+
+def _far_bunches():
+    return [wl.workload("gaussian_65536", n_override=20000)[0],
+            wl.workload("cold_sphere_2048", n_override=12289)[0],
+            mixed_charge_bunch(6000, seed=8), wl.workload("cold_sphere_2048", n_override=5)[0]]
+
+
+def _far_bound(f):
+    # plain FP32 separations of the high parts change a term by at most this
+    # fraction of its magnitude when the boxes are farther apart than U 2^-f
+    return 2.0 * math.sqrt(3.0) * 2.0 ** -23 * 2.0 ** f
+
+
+@pytest.mark.parametrize("K,far", [(1, 1), (2, 3), (4, 2)])
+def test_far_split_field_parity(orc, K, far):
+    bunches = _far_bunches()
+    say(f"far split field K={K} far={far} sizes={[b.n for b in bunches]} gap=3")
+    base = {"symmetric": 1, "i_per_lane": K}
+    with Sim(bunches, "mixed", tuning={**base, "far_split": far}, gap=3) as sim:
+        assert sim.tuning()["far_split"] == far
+        got_far = gpu_field(sim)
+        sim.set_tuning(**base, far_split=0)
+        got_near = gpu_field(sim)
+        slices = [sim.bunch_slice(k) for k in range(len(bunches))]
+        mask = np.ones(sim.n_total, bool)
+        for sl in slices:
+            mask[sl] = False
+    assert np.all(got_far["ex"][mask] == 0) and np.all(got_far["phi"][mask] == 0)
+    changed = 0
+    for k, b in enumerate(bunches):
+        sl = slices[k]
+        gf = {key: v[sl] for key, v in got_far.items()}
+        gn = {key: v[sl] for key, v in got_near.items()}
+        ref = oracle_field(orc, b)
+        check_field(gf, ref, TOL["mixed"], f"far={far} K={K} n={b.n}")
+        # the far path differs from hi/lo by no more than the per-term bound
+        d = np.linalg.norm(vec(gf) - vec(gn), axis=1)
+        lim = (_far_bound(far) * 1.01 + 1e-7) * ref["amag"]
+        assert np.all(d <= lim), (b.n, float((d / ref["amag"]).max()))
+        changed += int(np.any(d > 0))
+    assert changed >= 1  # the far path ran
+
+
+def test_far_split_push_graph_run_to_run_and_trajectory(orc):
+    b = wl.workload("gaussian_65536", n_override=9000)[0]
+    say("far split push == step_batched(graph), run-to-run, trajectory vs oracle, 6 steps")
+    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3, "graph_steps": 2}
+    res = []
+    for mode in ("push", "graph", "push"):
+        with Sim([b], "mixed", tuning=tun) as sim:
+            if mode == "push":
+                sim.push(6)
+            else:
+                sim.step_batched(6, graph=True)
+            res.append({k: sim.host(k) for k in ("x", "y", "z", "vx", "vy", "vz")})
+    for r in res[1:]:
+        for k in res[0]:
+            np.testing.assert_array_equal(res[0][k], r[k])
+    s = _state(b)
+    orc.vv(s, 6)
+    v_rms = math.sqrt(np.mean(s.vx ** 2 + s.vy ** 2 + s.vz ** 2))
+    ev = max(np.abs(res[0][k] - getattr(s, k)).max() for k in ("vx", "vy", "vz")) / v_rms
+    print(f"    far trajectory: max|dv|/v_rms={ev:.3e}", flush=True)
+    assert ev <= 1e-6
+
+
+def test_far_split_tuning_rules():
+    b = wl.workload("cold_sphere_2048", n_override=64)[0]
+    say("far split tuning validation")
+    with Sim([b], "mixed") as sim:
+        for bad in ({"symmetric": 0, "far_split": 2}, {"symmetric": 1, "i_per_lane": 1, "far_split": 9},
+                    {"symmetric": 1, "i_per_lane": 1, "far_split": -1}):
+            with pytest.raises(pp.PPError) as e:
+                sim.set_tuning(**bad)
+            assert e.value.status == pp.PP_ERR_INVALID_ARG
+    with Sim([b], "fp64") as sim:
+        with pytest.raises(pp.PPError):
+            sim.set_tuning(symmetric=1, i_per_lane=1, far_split=1)
