@@ -210,19 +210,22 @@ def main():
     sym = a.precision == "mixed" and used_tuning.get("symmetric", 0) == 1
     kernel = "pair_sym_kernel" if sym else f"pair_{a.precision}_kernel"
     roofline = None
-    if prof["launches"] > 0:
-        # one "launch" here is one field evaluation: the persistent kernel's
-        # single dispatch, or the symmetric schedule's diagonal + round dispatches
-        avg_s = prof["total_ms"] / prof["launches"] * 1e-3
-        achieved = FLOPS_PER_PAIR * pairs / avg_s / 1e12
+    if prof["launches"] > 0 and prof["evaluations"] > 0:
+        # pair-kernel time per field evaluation: the sum of its dispatches (one
+        # persistent dispatch, or one per band of rounds of the symmetric
+        # schedule), timed with HIP events on the stream they run on
+        eval_s = prof["total_ms"] / prof["evaluations"] * 1e-3
+        achieved = FLOPS_PER_PAIR * pairs / eval_s / 1e12
         roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                    "kernel": kernel, "avg_launch_ms": avg_s * 1e3, "launches": prof["launches"],
+                    "kernel": kernel, "kernel_ms_per_evaluation": eval_s * 1e3,
+                    "launches_per_evaluation": prof["launches"] / prof["evaluations"],
+                    "avg_launch_ms": prof["total_ms"] / prof["launches"],
                     "flops_per_pair": FLOPS_PER_PAIR, "flop_count": "20 per ordered pair interaction"}
         rec = stored_counters(a.workload, kernel) if not a.n else None
         if rec:
             roofline["traffic"] = rec["traffic_bytes_per_evaluation"]
-            counted = rec["counted_fp32_flops_per_evaluation"] / avg_s / 1e12
+            counted = rec["counted_fp32_flops_per_evaluation"] / eval_s / 1e12
             roofline["counted_fp32"] = {"achieved": counted, "frac": counted / PEAK_FP32_TFLOPS,
                                         "source": os.path.relpath(COUNTERS, ROOT)}
     sim.close()

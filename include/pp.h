@@ -195,17 +195,21 @@ pp_status pp_set_tuning(pp_ctx *ctx, const pp_tuning *tuning);
 
 /* Time one field evaluation of the current tiling with HIP events on the
  * context stream (synchronises): *ms receives the average over n_reps
- * evaluations of the pair-sum kernel alone; *pairs the ordered pair
- * interactions per evaluation (sum over bunches of n (n - 1)). */
+ * evaluations of the pair-sum stage (spatial sort if any, pair-sum
+ * dispatches, folds); *pairs the ordered pair interactions per evaluation
+ * (sum over bunches of n (n - 1)). */
 pp_status pp_time_field(pp_ctx *ctx, int32_t n_reps, double *ms, double *pairs);
 
 /* Kernel timing of the pair sum inside pp_push / pp_step_batched.  With
- * profiling on, every pair-sum launch made outside a hipGraph is bracketed by
- * HIP events on the context stream. */
+ * profiling on, every pair-sum kernel dispatch made outside a hipGraph is
+ * bracketed by HIP events on the context stream (the spatial sort and the
+ * folds of the symmetric schedule are not). */
 typedef struct {
-  int64_t launches;  /* pair-sum launches timed since the last read   */
-  double total_ms;   /* sum of their durations [ms]                   */
-  double pairs;      /* ordered pair interactions per launch          */
+  int64_t evaluations; /* field evaluations timed since the last read      */
+  int64_t launches;    /* pair-sum kernel dispatches among them (the
+                          symmetric schedule makes one per band of rounds) */
+  double total_ms;     /* sum of the dispatches' durations [ms]            */
+  double pairs;        /* ordered pair interactions per evaluation         */
 } pp_profile;
 pp_status pp_set_profiling(pp_ctx *ctx, int32_t enable);
 /* Synchronises, returns and resets the counters. */

@@ -73,29 +73,37 @@ constexpr int N_PLANES = 8;
 
 // Symmetric pair sum (Newton's third law): one rsq per unordered pair.  A bunch
 // is cut into blocks of SYM_WAVES * 64 * i_per_lane particles.  An item is the
-// receiver block I against the source block J != I (both sides accumulated),
+// receiver block I against the source block J != I (both sides evaluated),
 // or a diagonal item I == J (ordered pairs inside the block, self excluded).
-// Items are grouped into rounds: round d holds (I, I + d mod n_blocks), so in
-// one round every block receives exactly one receiver-side and one
-// source-side contribution; rounds run one launch after another, which fixes
-// the order of every addition.
+// Items are numbered by rounds: round 0 holds the diagonal items, round d >= 1
+// the pairs (I, I + d mod n_blocks), so in one round every block has at most
+// one receiver-side and one source-side partial.  Each item writes its two
+// partials into slots of its own, indexed by (round, block, side); a fold
+// kernel then adds the slots to the accumulators in round order.  Items of
+// many rounds therefore run in one launch, in any order, and the order of
+// every addition is still fixed.
 constexpr int SYM_WAVES = 8;
 constexpr int SYM_WG = SYM_WAVES * 64;
 constexpr int SYM_PLANES = 16;  // Si(xyz) Ci(xyz) Sj(xyz) Cj(xyz) Sip Cip Sjp Cjp
+constexpr int SLOT_PLANES = 8;  // per slot: S(xyz) C(xyz) Sp Cp
 
 struct SymItem {
   int32_t b;
   int32_t I;
   int32_t J;
-  int32_t diag;
+  int32_t r;  // round; 0 = diagonal item
 };
 
 struct SymArgs {
   const BunchDev* bunches;
   const SymItem* items;
   const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;
-  float* acc;   // SYM_PLANES planes of length P, indexed by particle
-  int64_t P;
+  // partial slots of the rounds [r0, r0 + rounds): float index
+  // (((r - r0) * nbt + block) * 2 + side) * SLOT_PLANES + plane) * block_size + offset,
+  // block = bunch's first block + I (side 0, receiver) or + J (side 1, source)
+  float* slot;
+  int32_t r0;
+  int32_t nbt;             // blocks over all bunches
   // near/far split (needs the spatial sort): a source group whose box is
   // farther than near_frac * U from the receiver block's box uses plain FP32
   // separations; near_frac = 0 keeps hi/lo separations everywhere
@@ -103,6 +111,19 @@ struct SymArgs {
   const float* gbox;       // [group][6]: min xyz, max xyz of the FP32 high parts
   const float* bbox;       // [block][6]
   const uint32_t* ubits;   // per-bunch bound U on |scaled coordinate| (float bits)
+};
+
+// Fold of the slots of rounds [r0, r1) into the accumulators (SYM_PLANES
+// planes of length n_total, indexed by position), in round order.
+struct SymFoldArgs {
+  const BunchDev* bunches;
+  const int32_t* bid;
+  int64_t n_total;
+  const float* slot;
+  float* acc;
+  int32_t r0, r1;
+  int32_t nbt;
+  int32_t block_size;
 };
 
 // Spatial sort (pp_sort.hip): keys per tile of the radix sort.
@@ -119,7 +140,8 @@ struct SortArgs {
   uint32_t* ubits;
   uint64_t *keys, *keys2;
   int32_t *vals, *vals2;
-  uint32_t* hist;
+  uint32_t* hist;          // 256 x sort tiles, digit-major
+  uint32_t* dtot;          // 256 digit totals
   int32_t* rank;           // sorted position of each particle
   float* gbox;
   float* bbox;
@@ -194,6 +216,7 @@ hipError_t launch_pair(const PairArgs& a, bool mixed, int i_per_lane, int sum_ti
 hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s);
 hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
                       hipStream_t s);
+hipError_t launch_sym_fold(const SymFoldArgs& a, bool with_phi, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
                        int32_t groups_per_block, hipStream_t s);
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,

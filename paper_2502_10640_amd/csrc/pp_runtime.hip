@@ -69,15 +69,18 @@ struct pp_ctx {
   size_t diag_doubles = 0;
   double** arrptr = nullptr;   // device table of state pointers for the finite check
   double *cmp_buf = nullptr;   // autotune comparison buffers (lazy)
-  ppk::SymItem* sitems = nullptr;  // symmetric schedule: diagonal launch, then one launch per round
+  ppk::SymItem* sitems = nullptr;  // symmetric schedule, round by round
   size_t sitems_cap = 0;
-  std::vector<std::pair<int32_t, int32_t>> launches;  // (first item, items) per launch
+  struct Band { int32_t first, count, r0, r1; };
+  std::vector<Band> bands;         // one item launch + one fold per band of rounds
   float* acc = nullptr;            // symmetric accumulators, SYM_PLANES x n_total
+  float* slot = nullptr;           // per-item partial slots of one band
+  size_t slot_bytes = 0;
   // spatial sort of the near/far split (allocated on first use)
   float* smir = nullptr;           // 7 planes in sorted order
   uint64_t* keys = nullptr;        // 2 x n_in (ping-pong)
   int32_t* vals = nullptr;         // 2 x n_in
-  uint32_t* hist = nullptr;        // 256 x sort tiles
+  uint32_t* hist = nullptr;        // 256 x (sort tiles + 1): histograms, then digit totals
   int32_t* rank = nullptr;         // sorted slot of each particle
   uint32_t* ubits = nullptr;       // per-bunch coordinate bound
   float* gbox = nullptr;           // 6 x 64-particle groups
@@ -96,8 +99,7 @@ struct pp_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
-  double prof_ms = 0.0;
-  int64_t prof_n = 0;
+  int64_t prof_evals = 0;
 
   std::string err;
   bool broken = false;
@@ -181,36 +183,57 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric schedule.  Blocks of SYM_WG * i_per_lane particles per bunch; launch
-// 0 holds every diagonal item, launch d >= 1 the block pairs (I, I + d mod nb)
+// Symmetric schedule.  Blocks of SYM_WG * i_per_lane particles per bunch; round
+// 0 holds every diagonal item, round d >= 1 the block pairs (I, I + d mod nb)
 // (for even nb and d = nb/2 only I < nb/2), so each unordered block pair occurs
-// exactly once and no two items of a launch share an accumulator.
+// exactly once and a round gives every block at most one partial per side.
+// Rounds are grouped into bands whose partial slots fit in kSlotBytes; a band
+// is one launch of all its items followed by one fold.
 // ---------------------------------------------------------------------------
+constexpr size_t kSlotBytes = size_t(8) << 30;
+
 pp_status build_sym(pp_ctx* c) {
   const int64_t BS = (int64_t)ppk::SYM_WG * c->tun.i_per_lane;
   std::vector<ppk::SymItem> items;
-  c->launches.clear();
+  std::vector<int64_t> round_first;
   int64_t maxr = 0;
+  round_first.push_back(0);
   for (int b = 0; b < c->nb; ++b) {
     const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
     if (nbk > INT32_MAX / 2) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule: too many blocks");
-    for (int64_t I = 0; I < nbk; ++I) items.push_back({b, (int32_t)I, (int32_t)I, 1});
+    for (int64_t I = 0; I < nbk; ++I) items.push_back({b, (int32_t)I, (int32_t)I, 0});
     maxr = std::max(maxr, nbk / 2);
   }
-  c->launches.push_back({0, (int32_t)items.size()});
   for (int64_t d = 1; d <= maxr; ++d) {
-    const size_t first = items.size();
+    round_first.push_back((int64_t)items.size());
     for (int b = 0; b < c->nb; ++b) {
       const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
       if (d > nbk / 2) continue;
       for (int64_t I = 0; I < nbk; ++I) {
         if (2 * d == nbk && I >= nbk / 2) continue;
-        items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), 0});
+        items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), (int32_t)d});
       }
     }
-    if (items.size() > first) c->launches.push_back({(int32_t)first, (int32_t)(items.size() - first)});
   }
+  round_first.push_back((int64_t)items.size());
   if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
+  const int64_t rounds = maxr + 1;
+  const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * sizeof(float);
+  const int64_t band = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
+  c->bands.clear();
+  for (int64_t r0 = 0; r0 < rounds; r0 += band) {
+    const int64_t r1 = std::min(rounds, r0 + band);
+    c->bands.push_back({(int32_t)round_first[r0], (int32_t)(round_first[r1] - round_first[r0]), (int32_t)r0,
+                        (int32_t)r1});
+  }
+  const size_t slot_need = (size_t)band * per_round;
+  if (slot_need > c->slot_bytes) {
+    if (c->slot) hipFree(c->slot);
+    c->slot = nullptr;
+    c->slot_bytes = 0;
+    PP_HIP(c, hipMalloc(&c->slot, slot_need));
+    c->slot_bytes = slot_need;
+  }
   if (items.size() > c->sitems_cap) {
     if (c->sitems) hipFree(c->sitems);
     c->sitems = nullptr;
@@ -227,7 +250,7 @@ pp_status build_sym(pp_ctx* c) {
     PP_HIP(c, dalloc(&c->smir, 7 * n));
     PP_HIP(c, dalloc(&c->keys, 2 * nin));
     PP_HIP(c, dalloc(&c->vals, 2 * nin));
-    PP_HIP(c, dalloc(&c->hist, 256 * tiles));
+    PP_HIP(c, dalloc(&c->hist, 256 * (tiles + 1)));  // + 256 digit totals
     PP_HIP(c, dalloc(&c->rank, n));
     PP_HIP(c, dalloc(&c->ubits, (size_t)c->nb));
     PP_HIP(c, dalloc(&c->gbox, 6 * (size_t)c->n_groups));
@@ -399,14 +422,20 @@ pp_status enqueue_pack(pp_ctx* c, bool drift, hipStream_t s) {
   return PP_OK;
 }
 
+// Events around one pair-sum dispatch when profiling.
+pp_status mark(pp_ctx* c, bool timed, bool begin, hipStream_t s) {
+  if (!timed) return PP_OK;
+  hipEvent_t e = take_event(c);
+  if (!e) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+  PP_HIP(c, hipEventRecord(e, s));
+  if (begin) c->ev_used.push_back({e, nullptr});
+  else c->ev_used.back().second = e;
+  return PP_OK;
+}
+
 pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    e0 = take_event(c);
-    e1 = take_event(c);
-    if (!e0 || !e1) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
-    PP_HIP(c, hipEventRecord(e0, s));
-  }
+  pp_status st;
+  if (timed) ++c->prof_evals;
   if (c->sym()) {
     ppk::SymArgs sa{};
     sa.bunches = c->dbunch;
@@ -414,8 +443,8 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
     sa.xh = c->plane(0); sa.yh = c->plane(1); sa.zh = c->plane(2);
     sa.xl = c->plane(3); sa.yl = c->plane(4); sa.zl = c->plane(5);
     sa.qt = c->plane(6);
-    sa.acc = c->acc;
-    sa.P = c->n_total;
+    sa.slot = c->slot;
+    sa.nbt = c->n_blocks;
     if (c->far()) {
       ppk::SortArgs so{};
       so.bunches = c->dbunch;
@@ -435,6 +464,10 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
       so.keys = c->keys; so.keys2 = c->keys + c->n_in;
       so.vals = c->vals; so.vals2 = c->vals + c->n_in;
       so.hist = c->hist;
+      {
+        const size_t tiles = ((size_t)c->n_in + ppk::SORT_TILE - 1) / ppk::SORT_TILE;
+        so.dtot = c->hist + 256 * tiles;
+      }
       so.rank = c->rank;
       so.gbox = c->gbox;
       so.bbox = c->bbox;
@@ -449,15 +482,28 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
       sa.bbox = c->bbox;
       sa.ubits = c->ubits;
     }
-    for (const auto& L : c->launches)
-      PP_HIP(c, ppk::launch_sym(sa, L.first, L.second, c->tun.i_per_lane, c->uniform_q, phi, s));
+    ppk::SymFoldArgs fa{};
+    fa.bunches = c->dbunch;
+    fa.bid = c->bid;
+    fa.n_total = c->n_total;
+    fa.slot = c->slot;
+    fa.acc = c->acc;
+    fa.nbt = c->n_blocks;
+    fa.block_size = ppk::SYM_WG * c->tun.i_per_lane;
+    for (const auto& B : c->bands) {
+      sa.r0 = B.r0;
+      if ((st = mark(c, timed, true, s)) != PP_OK) return st;
+      PP_HIP(c, ppk::launch_sym(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
+      if ((st = mark(c, timed, false, s)) != PP_OK) return st;
+      fa.r0 = B.r0;
+      fa.r1 = B.r1;
+      PP_HIP(c, ppk::launch_sym_fold(fa, phi, s));
+    }
   } else {
+    if ((st = mark(c, timed, true, s)) != PP_OK) return st;
     PP_HIP(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
                                grid_size(c), s));
-  }
-  if (timed) {
-    PP_HIP(c, hipEventRecord(e1, s));
-    c->ev_used.push_back({e0, e1});
+    if ((st = mark(c, timed, false, s)) != PP_OK) return st;
   }
   return PP_OK;
 }
@@ -537,8 +583,8 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   return true;
 }
 
-// Symmetric rounds pay off when every round keeps the GPU busy: the default
-// uses them when each bunch splits into at least 512 blocks.
+// Default: the symmetric schedule with the near/far split at D = U / 8 when
+// every bunch splits into at least 512 blocks, else the ordered-pair kernel.
 pp_tuning default_tuning(bool mixed, int64_t min_n) {
   pp_tuning t{};
   t.i_per_lane = mixed ? 2 : 1;
@@ -552,6 +598,7 @@ pp_tuning default_tuning(bool mixed, int64_t min_n) {
       if (min_n >= (int64_t)512 * ppk::SYM_WG * k) {
         t.symmetric = 1;
         t.i_per_lane = k;
+        t.far_split = 3;  // per-term change at most 3.3e-6 relative
         break;
       }
     }
@@ -728,7 +775,7 @@ void free_all(pp_ctx* c) {
   drop_graph(c);
   auto f = [](void* p) { if (p) hipFree(p); };
   f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
-  f(c->items); f(c->sitems); f(c->acc);
+  f(c->items); f(c->sitems); f(c->acc); f(c->slot);
   f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->bbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
   if (c->hpin) hipHostFree(c->hpin);
   for (auto& e : c->ev_pool) hipEventDestroy(e);
@@ -1051,10 +1098,12 @@ pp_status pp_get_profile(pp_ctx* c, pp_profile* out) {
     c->ev_pool.push_back(p.first);
     c->ev_pool.push_back(p.second);
   }
+  out->evaluations = c->prof_evals;
   out->launches = (int64_t)c->ev_used.size();
   out->total_ms = tot;
   out->pairs = c->pairs;
   c->ev_used.clear();
+  c->prof_evals = 0;
   return PP_OK;
 }
 

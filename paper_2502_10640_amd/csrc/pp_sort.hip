@@ -27,14 +27,38 @@ __global__ __launch_bounds__(256) void bound_zero_kernel(uint32_t* ubits, int32_
   if (b < nb) ubits[b] = 0u;
 }
 
+// each thread reduces 8 particles (stride 256 inside the workgroup's 2048),
+// flushing when the bunch changes; a wavefront whose lanes end in one bunch
+// reduces once more and makes a single atomic
+constexpr int BOUND_PER = 8;
+
 __global__ __launch_bounds__(256) void bound_kernel(SortArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_total) return;
-  const int b = a.bid[i];
-  if (b < 0) return;
-  const float m = fmaxf(fabsf(a.xh[i]), fmaxf(fabsf(a.yh[i]), fabsf(a.zh[i])));
-  // non-negative floats order like their bit patterns
-  atomicMax(&a.ubits[b], __float_as_uint(m));
+  const int64_t i0 = (int64_t)blockIdx.x * (256 * BOUND_PER) + threadIdx.x;
+  int b = -1;
+  float m = 0.f;
+  for (int k = 0; k < BOUND_PER; ++k) {
+    const int64_t i = i0 + (int64_t)k * 256;
+    if (i >= a.n_total) break;
+    const int bi = a.bid[i];
+    if (bi < 0) continue;
+    const float v = fmaxf(fabsf(a.xh[i]), fmaxf(fabsf(a.yh[i]), fabsf(a.zh[i])));
+    if (bi != b) {
+      // non-negative floats order like their bit patterns
+      if (b >= 0) atomicMax(&a.ubits[b], __float_as_uint(m));
+      b = bi;
+      m = v;
+    } else {
+      m = fmaxf(m, v);
+    }
+  }
+  const int b0 = __shfl(b, 0);
+  if (__all(b == b0)) {
+    if (b0 < 0) return;
+    for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+    if ((threadIdx.x & 63) == 0) atomicMax(&a.ubits[b0], __float_as_uint(m));
+  } else if (b >= 0) {
+    atomicMax(&a.ubits[b], __float_as_uint(m));
+  }
 }
 
 // ---- keys --------------------------------------------------------------------
@@ -89,27 +113,59 @@ __global__ __launch_bounds__(RT) void hist_kernel(const uint64_t* __restrict__ k
   hist[(int64_t)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
 
-// exclusive scan of hist (digit-major, length 256 * n_tiles), one workgroup
-__global__ __launch_bounds__(1024) void scan_kernel(uint32_t* __restrict__ hist, int64_t len) {
-  __shared__ uint32_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (len + 1023) / 1024;
-  const int64_t s0 = tid * per, s1 = min(len, s0 + per);
+// Exclusive scan of hist (digit-major: hist[d * n_tiles + t]) in two
+// launches of one workgroup per digit: digit totals, then each digit's base
+// (sum of the totals of smaller digits) plus the scan of its own row.
+__global__ __launch_bounds__(256) void digit_total_kernel(const uint32_t* __restrict__ hist, int32_t n_tiles,
+                                                          uint32_t* __restrict__ tot) {
+  __shared__ uint32_t part[256];
+  const int d = blockIdx.x, tid = threadIdx.x;
   uint32_t sum = 0u;
-  for (int64_t e = s0; e < s1; ++e) sum += hist[e];
+  for (int t = tid; t < n_tiles; t += 256) sum += hist[(int64_t)d * n_tiles + t];
   part[tid] = sum;
   __syncthreads();
-  // Hillis-Steele inclusive scan of the 1024 segment sums
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = tid >= off ? part[tid - off] : 0u;
-    __syncthreads();
-    part[tid] += v;
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
     __syncthreads();
   }
-  uint32_t run = tid > 0 ? part[tid - 1] : 0u;
-  for (int64_t e = s0; e < s1; ++e) {
-    const uint32_t v = hist[e];
-    hist[e] = run;
+  if (tid == 0) tot[d] = part[0];
+}
+
+// inclusive Hillis-Steele scan of v over the 256 threads of the workgroup
+__device__ uint32_t block_scan_incl(uint32_t v, uint32_t* buf) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t x = tid >= off ? buf[tid - off] : 0u;
+    __syncthreads();
+    buf[tid] += x;
+    __syncthreads();
+  }
+  const uint32_t r = buf[tid];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void digit_scan_kernel(uint32_t* __restrict__ hist, int32_t n_tiles,
+                                                         const uint32_t* __restrict__ tot) {
+  __shared__ uint32_t buf[256];
+  const int d = blockIdx.x, tid = threadIdx.x;
+  // base of digit d: exclusive prefix of the digit totals
+  const uint32_t incl = block_scan_incl(tot[tid], buf);
+  __shared__ uint32_t base;
+  if (tid == d) base = incl - tot[tid];
+  __syncthreads();
+  // this digit's row: thread tid scans a contiguous segment
+  const int per = (n_tiles + 255) / 256;
+  const int t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
+  uint32_t* row = hist + (int64_t)d * n_tiles;
+  uint32_t seg = 0u;
+  for (int t = t0; t < t1; ++t) seg += row[t];
+  uint32_t run = base + block_scan_incl(seg, buf) - seg;
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = row[t];
+    row[t] = run;
     run += v;
   }
 }
@@ -173,23 +229,40 @@ __global__ __launch_bounds__(256) void gather_kernel(SortArgs a) {
   a.sqt[p] = a.qt[i];
 }
 
-// one thread per group of 64 sorted particles: box of the FP32 high parts
-__global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_total) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_groups_total) return;
-  // find the bunch: groups are numbered bunch by bunch
-  int b = 0;
-  while (b + 1 < a.nb && a.bunches[b + 1].gbase <= g) ++b;
-  const BunchDev& B = a.bunches[b];
-  const int64_t l0 = (int64_t)(g - B.gbase) * 64;
-  const int64_t l1 = min(B.n, l0 + 64);
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t l = l0; l < l1; ++l) {
-    const int64_t p = B.off + l;
-    const float v[3] = {a.sxh[p], a.syh[p], a.szh[p]};
-    for (int c = 0; c < 3; ++c) { lo[c] = fminf(lo[c], v[c]); hi[c] = fmaxf(hi[c], v[c]); }
+// bunch of group g (groups are numbered bunch by bunch)
+__device__ __forceinline__ int bunch_of_group(const BunchDev* bunches, int nb, int g) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bunches[mid].gbase <= g) lo = mid;
+    else hi = mid - 1;
   }
-  for (int c = 0; c < 3; ++c) { a.gbox[(int64_t)g * 6 + c] = lo[c]; a.gbox[(int64_t)g * 6 + 3 + c] = hi[c]; }
+  return lo;
+}
+
+// one wavefront per group of 64 sorted particles: box of the FP32 high parts
+__global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_total) {
+  const int g = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int l = threadIdx.x & 63;
+  if (g >= n_groups_total) return;  // uniform over the wavefront
+  const BunchDev& B = a.bunches[bunch_of_group(a.bunches, a.nb, g)];
+  const int64_t li = (int64_t)(g - B.gbase) * 64 + l;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (li < B.n) {
+    const int64_t p = B.off + li;
+    lo[0] = hi[0] = a.sxh[p];
+    lo[1] = hi[1] = a.syh[p];
+    lo[2] = hi[2] = a.szh[p];
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fminf(lo[c], __shfl_xor(lo[c], d));
+      hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], d));
+    }
+  }
+  const float v = l == 0 ? lo[0] : l == 1 ? lo[1] : l == 2 ? lo[2] : l == 3 ? hi[0] : l == 4 ? hi[1] : hi[2];
+  if (l < 6) a.gbox[(int64_t)g * 6 + l] = v;
 }
 
 // one thread per symmetric block: union of its groups' boxes
@@ -217,7 +290,7 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
                        int32_t groups_per_block, hipStream_t s) {
   hipLaunchKernelGGL(bound_zero_kernel, dim3(nblk(a.nb, 256)), dim3(256), 0, s, a.ubits, a.nb);
-  hipLaunchKernelGGL(bound_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bound_kernel, dim3(nblk(a.n_total, 256 * BOUND_PER)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a);
   const int32_t n_tiles = (int32_t)nblk(a.n_in, TILE);
   uint64_t* kin = a.keys;
@@ -228,7 +301,8 @@ hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, 
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     hipLaunchKernelGGL(hist_kernel, dim3(n_tiles), dim3(RT), 0, s, kin, a.n_in, shift, a.hist, n_tiles);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a.hist, (int64_t)256 * n_tiles);
+    hipLaunchKernelGGL(digit_total_kernel, dim3(256), dim3(256), 0, s, a.hist, n_tiles, a.dtot);
+    hipLaunchKernelGGL(digit_scan_kernel, dim3(256), dim3(256), 0, s, a.hist, n_tiles, a.dtot);
     hipLaunchKernelGGL(scatter_kernel, dim3(n_tiles), dim3(RT), 0, s, kin, vin, kout, vout, a.n_in, shift, a.hist,
                        n_tiles);
     uint64_t* tk = kin; kin = kout; kout = tk;
@@ -237,7 +311,8 @@ hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, 
   SortArgs g = a;
   g.vals = vin;  // sorted order after an even or odd number of passes
   hipLaunchKernelGGL(gather_kernel, dim3(nblk(a.n_in, 256)), dim3(256), 0, s, g);
-  hipLaunchKernelGGL(gbox_kernel, dim3(nblk(n_groups_total, 256)), dim3(256), 0, s, g, n_groups_total);
+  hipLaunchKernelGGL(gbox_kernel, dim3(nblk((int64_t)n_groups_total * 64, 256)), dim3(256), 0, s, g,
+                     n_groups_total);
   hipLaunchKernelGGL(bbox_kernel, dim3(nblk(n_blocks_total, 256)), dim3(256), 0, s, g, n_blocks_total,
                      groups_per_block);
   return hipGetLastError();

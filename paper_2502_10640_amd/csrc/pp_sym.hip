@@ -9,20 +9,21 @@
 // An item pairs receiver block I (held in VGPRs, i_per_lane per lane, 8 waves)
 // with source block J, swept in groups of 64 sources staged in LDS.  In step s
 // of a group, lane l meets source (l + s) mod 64 (every lane reads a distinct
-// LDS address).  The source-side partial of that source travels with it: after
+// LDS address; the group is stored twice so that the address needs no wrap).  The source-side partial of that source travels with it: after
 // each step every lane takes over the partial of its upper neighbour
 // (ds_bpermute, an explicit cross-lane move).  Every 16 steps the partials are
 // handed to their sources' home lanes (lane l owns source l) and added there
 // with two-sum.  After the group the 8 waves' pairs are combined in wave order
-// and added (two-sum) to the block's source-side accumulator in HBM.  The receiver side is a plain FP32 sum over
-// each group of 64 sources, two-summed into registers, and added to the
-// receiver-side accumulator at the end of the item.
+// and stored as the source-side partial (S, C) of the item.  The receiver side
+// is a plain FP32 sum over each group of 64 sources, two-summed into
+// registers, and stored as the receiver-side partial at the end of the item.
 //
-// Diagonal items (I == J) evaluate the ordered pairs inside one block with the
-// self term masked, write the receiver-side accumulator and clear the
-// source-side one; they run first.  Rounds of off-diagonal items follow, one
-// launch per round; within a round no two items touch the same accumulator,
-// and the order of rounds fixes the order of every addition.
+// Diagonal items (I == J, round 0) evaluate the ordered pairs inside one block
+// with the self term masked and have a receiver-side partial only.  Every
+// item writes slots of its own, so the items of many rounds run in one launch
+// in any order; the fold kernel then adds the slots of each position in round
+// order (receiver side and source side kept apart), which fixes the order of
+// every addition.
 #include "pp_device.h"
 #include "pp_internal.h"
 
@@ -36,6 +37,12 @@ namespace {
 // zeros in both directions.
 constexpr float SENTINEL = 1.5e19f;
 
+// steps of a source group unrolled per loop iteration (divides 16)
+#ifndef SYM_UNROLL
+#define SYM_UNROLL 16
+#endif
+static_assert(16 % SYM_UNROLL == 0, "the hand-off period is a whole number of iterations");
+
 __device__ __forceinline__ float lane_read(float v, int src_lane) {
   // value of v in lane src_lane of this wavefront (ds_bpermute: LDS crossbar, no LDS memory)
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
@@ -48,77 +55,86 @@ __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, cons
                                             const float (&zl)[K], const float (&qi)[K], float eps2,
                                             float (&ti)[3][K], float (&tip)[K], float (&Sj)[4], float (&Cj)[4]) {
   // aj: plain partial of the source met in this step, (l + s) mod 64; it moves
-  // one lane down every step so that it stays with its source.
+  // one lane down every step so that it stays with its source.  The source
+  // group is stored twice in LDS (entries 64..127 repeat 0..63), so step s
+  // reads entry l + s with no wrap, at an immediate offset from the base of
+  // its block of 16 steps.
   float aj[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int s = 0; s < 64; ++s) {
-    const int jj = (l + s) & 63;
-    const float4 h = sjh[jj];
-    float dx[K], dy[K], dz[K], r2[K], inv[K];
-    if (FAR) {
-      // far group: plain FP32 separations of the high parts
+  for (int s0 = 0; s0 < 64; s0 += SYM_UNROLL) {
+    const float4* hb = sjh + (l + s0);
+    const float4* lb = sjl + (l + s0);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        dx[k] = xh[k] - h.x;
-        dy[k] = yh[k] - h.y;
-        dz[k] = zh[k] - h.z;
-      }
-    } else {
-      const float4 lo = sjl[jj];
+    for (int u = 0; u < SYM_UNROLL; ++u) {
+      const int s = s0 + u;
+      const float4 h = hb[u];
+      float dx[K], dy[K], dz[K], r2[K], inv[K];
+      if (FAR) {
+        // far group: plain FP32 separations of the high parts
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        dx[k] = (xh[k] - h.x) + (xl[k] - lo.x);
-        dy[k] = (yh[k] - h.y) + (yl[k] - lo.y);
-        dz[k] = (zh[k] - h.z) + (zl[k] - lo.z);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      r2[k] = fmaf(dz[k], dz[k], fmaf(dy[k], dy[k], fmaf(dx[k], dx[k], eps2)));
-      if (DIAG) {
-        // self term: receiver group gsel + k, source lane jj == l at s == 0
-        if (s == 0 && gsel == k) r2[k] = __builtin_inff();
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) inv[k] = __builtin_amdgcn_rsqf(r2[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float s3 = (inv[k] * inv[k]) * inv[k];
-      const float fi = UQ ? s3 : h.w * s3;
-      ti[0][k] = fmaf(dx[k], fi, ti[0][k]);
-      ti[1][k] = fmaf(dy[k], fi, ti[1][k]);
-      ti[2][k] = fmaf(dz[k], fi, ti[2][k]);
-      if (PHI) tip[k] += UQ ? inv[k] : h.w * inv[k];
-      if (!DIAG) {
-        const float fj = UQ ? s3 : qi[k] * s3;
-        aj[0] = fmaf(-dx[k], fj, aj[0]);
-        aj[1] = fmaf(-dy[k], fj, aj[1]);
-        aj[2] = fmaf(-dz[k], fj, aj[2]);
-        if (PHI) aj[3] += UQ ? inv[k] : qi[k] * inv[k];
-      }
-    }
-    if (!DIAG) {
-      if ((s & 15) == 15) {
-        // hand each partial to its source's home lane: lane l receives the
-        // partial of source l from lane (l - s) mod 64, adds it with two-sum
-#pragma unroll
-        for (int q = 0; q < (PHI ? 4 : 3); ++q) {
-          const float m = lane_read(aj[q], (l - s) & 63);
-          two_sum(Sj[q], Cj[q], m);
-          aj[q] = 0.f;
+        for (int k = 0; k < K; ++k) {
+          dx[k] = xh[k] - h.x;
+          dy[k] = yh[k] - h.y;
+          dz[k] = zh[k] - h.z;
         }
       } else {
-        // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
+        const float4 lo = lb[u];
 #pragma unroll
-        for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read(aj[q], (l + 1) & 63);
+        for (int k = 0; k < K; ++k) {
+          dx[k] = (xh[k] - h.x) + (xl[k] - lo.x);
+          dy[k] = (yh[k] - h.y) + (yl[k] - lo.y);
+          dz[k] = (zh[k] - h.z) + (zl[k] - lo.z);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        r2[k] = fmaf(dz[k], dz[k], fmaf(dy[k], dy[k], fmaf(dx[k], dx[k], eps2)));
+        if (DIAG) {
+          // self term: receiver group gsel + k, source lane l at step 0
+          if (s == 0 && gsel == k) r2[k] = __builtin_inff();
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) inv[k] = __builtin_amdgcn_rsqf(r2[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float s3 = (inv[k] * inv[k]) * inv[k];
+        const float fi = UQ ? s3 : h.w * s3;
+        ti[0][k] = fmaf(dx[k], fi, ti[0][k]);
+        ti[1][k] = fmaf(dy[k], fi, ti[1][k]);
+        ti[2][k] = fmaf(dz[k], fi, ti[2][k]);
+        if (PHI) tip[k] += UQ ? inv[k] : h.w * inv[k];
+        if (!DIAG) {
+          const float fj = UQ ? s3 : qi[k] * s3;
+          aj[0] = fmaf(-dx[k], fj, aj[0]);
+          aj[1] = fmaf(-dy[k], fj, aj[1]);
+          aj[2] = fmaf(-dz[k], fj, aj[2]);
+          if (PHI) aj[3] += UQ ? inv[k] : qi[k] * inv[k];
+        }
+      }
+      if (!DIAG) {
+        if ((s & 15) == 15) {
+          // hand each partial to its source's home lane: lane l receives the
+          // partial of source l from lane (l - s) mod 64, adds it with two-sum
+          const int from = (l - s) & 63;
+#pragma unroll
+          for (int q = 0; q < (PHI ? 4 : 3); ++q) {
+            const float m = lane_read(aj[q], from);
+            two_sum(Sj[q], Cj[q], m);
+            aj[q] = 0.f;
+          }
+        } else {
+          // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
+#pragma unroll
+          for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read(aj[q], (l + 1) & 63);
+        }
       }
     }
   }
 }
 
 struct SymShared {
-  float4 sjh[64];                // source group: hi position, normalised charge
-  float4 sjl[64];                // source group: lo position
+  float4 sjh[128];               // source group twice: hi position, normalised charge
+  float4 sjl[128];               // source group twice: lo position
   float xw[SYM_WAVES][8][64];    // per-wave two-sum pairs for the cross-wave combine
 };
 
@@ -135,6 +151,9 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
   constexpr int BS = SYM_WAVES * 64 * K;
   const int ibase = it.I * BS, jbase0 = it.J * BS;
   const float eps2 = B.eps2s;
+  const int64_t rho = it.r - a.r0;
+  float* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
+  float* sslot = a.slot + ((rho * a.nbt + B.bbase + it.J) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
 
   // near/far split: receiver block box and threshold (uniform over the item)
   const bool split = !DIAG && a.near_frac > 0.f;
@@ -173,14 +192,19 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     __syncthreads();  // LDS of the previous group is free
     if (w == 0) {
       const int lj = jg + l;
+      float4 h, lo;
       if (lj < n) {
         const int64_t gi = off + lj;
-        sjh[l] = make_float4(a.xh[gi], a.yh[gi], a.zh[gi], UQ ? 1.f : a.qt[gi]);
-        sjl[l] = make_float4(a.xl[gi], a.yl[gi], a.zl[gi], 0.f);
+        h = make_float4(a.xh[gi], a.yh[gi], a.zh[gi], UQ ? 1.f : a.qt[gi]);
+        lo = make_float4(a.xl[gi], a.yl[gi], a.zl[gi], 0.f);
       } else {
-        sjh[l] = make_float4(SENTINEL, SENTINEL, SENTINEL, 0.f);
-        sjl[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+        h = make_float4(SENTINEL, SENTINEL, SENTINEL, 0.f);
+        lo = make_float4(0.f, 0.f, 0.f, 0.f);
       }
+      sjh[l] = h;
+      sjh[l + 64] = h;
+      sjl[l] = lo;
+      sjl[l + 64] = lo;
     }
     __syncthreads();
 
@@ -224,58 +248,33 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
       }
       __syncthreads();
       // one thread per (source, component): waves 0-3 combine the 8 waves'
-      // pairs in wave order and add them to the source-side accumulator
+      // pairs in wave order and store the source-side partial
       const int q = tid >> 6;  // 0..2 field components, 3 potential
       if (q < (PHI ? 4 : 3)) {
         float S = xw[0][q][l], C = xw[0][4 + q][l];
         for (int ww = 1; ww < SYM_WAVES; ++ww) two_sum_pair(S, C, xw[ww][q][l], xw[ww][4 + q][l]);
-        const int lj = jg + l;
-        if (lj < n) {
-          const int64_t slot = off + lj;
-          const int ps = q < 3 ? 6 + q : 14, pc = q < 3 ? 9 + q : 15;
-          float gs = a.acc[ps * a.P + slot], gc = a.acc[pc * a.P + slot];
-          two_sum_pair(gs, gc, S, C);
-          a.acc[ps * a.P + slot] = gs;
-          a.acc[pc * a.P + slot] = gc;
+        if (jg + l < n) {
+          const int o = g * 64 + l;
+          sslot[(q < 3 ? q : 6) * BS + o] = S;
+          sslot[(q < 3 ? 3 + q : 7) * BS + o] = C;
         }
       }
     }
   }
 
-  // receiver side
+  // receiver-side partial
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int li = ibase + (w * K + k) * 64 + l;
-    if (li >= n) continue;
-    const int64_t slot = off + li;
-    if (DIAG) {
+    const int o = (w * K + k) * 64 + l;
+    if (ibase + o >= n) continue;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        a.acc[c * a.P + slot] = Si[c][k];
-        a.acc[(3 + c) * a.P + slot] = Ci[c][k];
-        a.acc[(6 + c) * a.P + slot] = 0.f;
-        a.acc[(9 + c) * a.P + slot] = 0.f;
-      }
-      if (PHI) {
-        a.acc[12 * a.P + slot] = Sip[k];
-        a.acc[13 * a.P + slot] = Cip[k];
-        a.acc[14 * a.P + slot] = 0.f;
-        a.acc[15 * a.P + slot] = 0.f;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float gs = a.acc[c * a.P + slot], gc = a.acc[(3 + c) * a.P + slot];
-        two_sum_pair(gs, gc, Si[c][k], Ci[c][k]);
-        a.acc[c * a.P + slot] = gs;
-        a.acc[(3 + c) * a.P + slot] = gc;
-      }
-      if (PHI) {
-        float gs = a.acc[12 * a.P + slot], gc = a.acc[13 * a.P + slot];
-        two_sum_pair(gs, gc, Sip[k], Cip[k]);
-        a.acc[12 * a.P + slot] = gs;
-        a.acc[13 * a.P + slot] = gc;
-      }
+    for (int c = 0; c < 3; ++c) {
+      rslot[c * BS + o] = Si[c][k];
+      rslot[(3 + c) * BS + o] = Ci[c][k];
+    }
+    if (PHI) {
+      rslot[6 * BS + o] = Sip[k];
+      rslot[7 * BS + o] = Cip[k];
     }
   }
 }
@@ -284,7 +283,7 @@ template <int K, bool UQ, bool PHI>
 __global__ __launch_bounds__(SYM_WG) void pair_sym_kernel(SymArgs a, int32_t first) {
   __shared__ SymShared sh;
   const SymItem it = a.items[first + blockIdx.x];
-  if (it.diag)
+  if (it.r == 0)
     sym_item<K, UQ, PHI, true>(a, it, sh);
   else
     sym_item<K, UQ, PHI, false>(a, it, sh);
@@ -302,7 +301,83 @@ hipError_t go_sym_k(const SymArgs& a, int32_t first, int32_t count, bool uq, boo
   return phi ? go_sym<K, false, true>(a, first, count, s) : go_sym<K, false, false>(a, first, count, s);
 }
 
+// One thread per position: adds the slots of rounds [r0, r1) in round order to
+// the accumulators; round 0 (diagonal items) starts them.
+template <bool PHI>
+__global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_total) return;
+  const int b = a.bid[p];
+  if (b < 0) return;
+  const BunchDev& B = a.bunches[b];
+  const int BS = a.block_size;
+  const int l = (int)(p - B.off);
+  const int X = l / BS, o = l - X * BS;
+  const int nbk = (int)((B.n + BS - 1) / BS), half = nbk / 2;
+  constexpr int NQ = PHI ? 4 : 3;
+  const int64_t P = a.n_total;
+  float rs[NQ], rc[NQ], ss[NQ], sc[NQ];
+  // accumulator planes of component q: receiver S, C and source S, C
+  auto pl = [](int q, int k) { return q < 3 ? q + 3 * k : 12 + k; };
+  if (a.r0 == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rs[q] = rc[q] = ss[q] = sc[q] = 0.f;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      rs[q] = a.acc[pl(q, 0) * P + p];
+      rc[q] = a.acc[pl(q, 1) * P + p];
+      ss[q] = a.acc[pl(q, 2) * P + p];
+      sc[q] = a.acc[pl(q, 3) * P + p];
+    }
+  }
+  const int64_t sl = (int64_t)SLOT_PLANES * BS;
+  for (int r = a.r0; r < a.r1; ++r) {
+    const float* base = a.slot + ((int64_t)(r - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+    if (r == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        rs[q] = base[(q < 3 ? q : 6) * BS];
+        rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+      }
+      continue;
+    }
+    if (r > half) continue;  // the bunch has no item in this round
+    // receiver side: item (X, X + r); source side: item (X - r, X).  With an
+    // even block count the round r = nbk / 2 holds only the items with I < nbk / 2.
+    const bool has_r = !(2 * r == nbk && X >= half);
+    const int js = X - r < 0 ? X - r + nbk : X - r;
+    const bool has_s = !(2 * r == nbk && js >= half);
+    if (has_r) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        two_sum_pair(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+    }
+    if (has_s) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        two_sum_pair(ss[q], sc[q], base[sl + (q < 3 ? q : 6) * BS], base[sl + (q < 3 ? 3 + q : 7) * BS]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    a.acc[pl(q, 0) * P + p] = rs[q];
+    a.acc[pl(q, 1) * P + p] = rc[q];
+    a.acc[pl(q, 2) * P + p] = ss[q];
+    a.acc[pl(q, 3) * P + p] = sc[q];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_sym_fold(const SymFoldArgs& a, bool with_phi, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.n_total + 255) / 256);
+  if (with_phi)
+    hipLaunchKernelGGL(sym_fold_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(sym_fold_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
                       hipStream_t s) {

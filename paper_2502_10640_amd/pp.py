@@ -79,7 +79,8 @@ class Tuning(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("pairs", ctypes.c_double)]
+    _fields_ = [("evaluations", ctypes.c_int64), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("pairs", ctypes.c_double)]
 
 
 _LIB = None
@@ -202,7 +203,7 @@ def pp_set_profiling(ctx, enable: bool) -> None:
 def pp_get_profile(ctx) -> dict:
     p = Profile()
     _check(load().pp_get_profile(ctx, ctypes.byref(p)), ctx)
-    return {"launches": p.launches, "total_ms": p.total_ms, "pairs": p.pairs}
+    return {"evaluations": p.evaluations, "launches": p.launches, "total_ms": p.total_ms, "pairs": p.pairs}
 
 
 def pp_sync(ctx) -> None:
