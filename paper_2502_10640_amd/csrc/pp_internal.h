@@ -197,6 +197,12 @@ enum DiagSlot : int32_t {
 };
 constexpr int D_N2 = D_NREC - D_N1;
 
+// Host record of one bunch written by the diagnostics kernels: the 30 values
+// of pp_diag from `kinetic` through `v_max` in declaration order, then the
+// non-finite count.
+constexpr int D_OUT_VALUES = 30;
+constexpr int D_OUT = D_OUT_VALUES + 1;
+
 struct DiagArgs {
   const BunchDev* bunches;
   const double *x, *y, *z, *vx, *vy, *vz, *q, *m, *phi;

@@ -571,7 +571,6 @@ __global__ __launch_bounds__(WG) void diag_pass2_kernel(DiagArgs a) {
 // out layout per bunch (doubles, pp_diag order from `kinetic` on):
 // kinetic potential total momentum[3] com[3] com_velocity[3] emittance[3]
 // emittance_centered[3] x_rms[3] x_max[3] v_rms[3] v_max[3] nonfinite
-constexpr int D_OUT = 3 + 3 * 10 + 1;
 
 __global__ void diag_final2_kernel(DiagArgs a, double* out) {
   const int b = blockIdx.x;
@@ -602,7 +601,7 @@ __global__ void diag_final2_kernel(DiagArgs a, double* out) {
     o[24 + c] = sqrt(vv);
     o[27 + c] = rb[D_VMAX0 + c];
   }
-  o[30 + 3] = rb[D_NONFIN];
+  o[D_OUT_VALUES] = rb[D_NONFIN];
 }
 
 template <int K, bool UQ, bool PHI>

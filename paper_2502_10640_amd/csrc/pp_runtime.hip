@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1012,7 +1013,7 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
   if (!out) return set_err(c, PP_ERR_INVALID_ARG, "out is NULL");
   const int G = (int)std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / c->nb));
   if (!c->phi) PP_HIP(c, dalloc(&c->phi, (size_t)c->n_total));
-  const size_t need = (size_t)c->nb * ((size_t)G * ppk::D_N1 + ppk::D_NREC + 34);
+  const size_t need = (size_t)c->nb * ((size_t)G * ppk::D_N1 + ppk::D_NREC + ppk::D_OUT);
   if (need > c->diag_doubles) {
     if (c->diag_buf) hipFree(c->diag_buf);
     c->diag_buf = nullptr;
@@ -1029,21 +1030,23 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
   d.vx = c->st.vx; d.vy = c->st.vy; d.vz = c->st.vz;
   d.q = c->st.q; d.m = c->st.m; d.phi = c->phi;
   d.weight = c->dweight;
-  d.part = c->diag_buf + (size_t)c->nb * (ppk::D_NREC + 34);
+  d.part = c->diag_buf + (size_t)c->nb * (ppk::D_NREC + ppk::D_OUT);
   d.rec = c->diag_buf;
   d.G = G;
   PP_HIP(c, ppk::launch_diag(d, c->nb, c->stream));
-  std::vector<double> res((size_t)c->nb * 34);
+  std::vector<double> res((size_t)c->nb * ppk::D_OUT);
   if ((s = d2h(c, res.data(), c->diag_buf + (size_t)c->nb * ppk::D_NREC, res.size() * sizeof(double))) != PP_OK)
     return s;
   for (int b = 0; b < c->nb; ++b) {
-    const double* r = &res[(size_t)b * 34];
+    const double* r = &res[(size_t)b * ppk::D_OUT];
     pp_diag& o = out[b];
     o.step = c->step;
     o.n = c->hb[b].n;
     o.time = (double)c->step * c->hb[b].dt;
-    std::memcpy(&o.kinetic, r, 33 * sizeof(double));
-    o.nonfinite = (int64_t)std::llround(r[33]);
+    static_assert(offsetof(pp_diag, nonfinite) - offsetof(pp_diag, kinetic) == ppk::D_OUT_VALUES * sizeof(double),
+                  "the device record matches pp_diag from kinetic through v_max");
+    std::memcpy(&o.kinetic, r, ppk::D_OUT_VALUES * sizeof(double));
+    o.nonfinite = (int64_t)std::llround(r[ppk::D_OUT_VALUES]);
   }
   return PP_OK;
 }

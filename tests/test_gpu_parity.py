@@ -159,22 +159,21 @@ def test_push_parity(orc, prec):
     assert er <= tol_r and ev <= tol_v
 
 
-DIAG_SKIP = pytest.mark.skip(reason=(
-    "pp_diagnostics is kept off the GPU this round: runs that called it ended in a host SIGSEGV "
-    "(Python heap corrupted) while every other path passes; a CPU AddressSanitizer build of the same "
-    "library replays the sequence cleanly, so no mistake in this code has been shown yet"))
-
 DIAG_SCALARS = ("kinetic", "potential", "total")
 DIAG_VECTORS = ("com", "com_velocity", "emittance", "emittance_centered", "x_rms", "x_max", "v_rms", "v_max")
 
 
-@DIAG_SKIP
-@pytest.mark.parametrize("prec", PRECS)
-def test_diagnostics_parity(orc, prec):
+DIAG_TUNING = {"fp64": None, "mixed": None,
+               "mixed_symmetric_far": {"symmetric": 1, "i_per_lane": 1, "far_split": 3}}
+
+
+@pytest.mark.parametrize("variant", list(DIAG_TUNING))
+def test_diagnostics_parity(orc, variant):
     """GPU diagnostics against the oracle's on the GPU's own state."""
+    prec = "fp64" if variant == "fp64" else "mixed"
     b = wl.workload("gaussian_65536", n_override=4096)[0]
-    say(f"diagnostics {prec} n={b.n}")
-    with Sim([b], prec) as sim:
+    say(f"diagnostics {variant} n={b.n}")
+    with Sim([b], prec, tuning=DIAG_TUNING[variant]) as sim:
         sim.push(5)
         d = sim.diagnostics()[0]
         st = {k: sim.host(k) for k in ("x", "y", "z", "vx", "vy", "vz")}
@@ -197,6 +196,26 @@ def test_diagnostics_parity(orc, prec):
     assert np.abs(np.array(d["momentum"]) - ref["momentum"]).max() <= 1e-13 * pscale
     assert d["nonfinite"] == 0 and d["step"] == 5 and d["n"] == b.n
     assert d["time"] == pytest.approx(5 * b.dt, rel=1e-15, abs=0)
+
+
+def test_diagnostics_write_only_the_callers_records():
+    """pp_diagnostics fills exactly one pp_diag per bunch: a guard record after
+    the caller's array stays untouched (an earlier version copied two doubles
+    too many per record and corrupted the caller's heap)."""
+    import ctypes
+    bunches = [wl.workload("cold_sphere_2048", n_override=n)[0] for n in (300, 77, 1)]
+    say("diagnostics guard record, 3 bunches")
+    with Sim(bunches, "mixed") as sim:
+        nb = len(bunches)
+        buf = (pp.Diag * (nb + 1))()
+        size = ctypes.sizeof(pp.Diag)
+        ctypes.memset(ctypes.addressof(buf) + nb * size, 0x5A, size)
+        st = pp.load().pp_diagnostics(sim.ctx, buf)
+        assert st == pp.PP_OK, pp.pp_last_error(sim.ctx)
+        assert ctypes.string_at(ctypes.addressof(buf) + nb * size, size) == b"\x5a" * size
+        assert [buf[k].n for k in range(nb)] == [b.n for b in bunches]
+        assert all(buf[k].nonfinite == 0 for k in range(nb))
+        assert buf[2].potential == 0.0 and buf[0].potential > 0.0
 
 
 @pytest.mark.parametrize("prec", PRECS)
