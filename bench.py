@@ -58,9 +58,11 @@ def parse():
     p.add_argument("--tuning", default="", help="k=v,... tiling override (i_per_lane, sum_tile, ...)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
-    p.add_argument("--mode", default="throughput", choices=["throughput", "drift"],
+    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper"],
                    help="drift: run --steps steps in mixed and FP64 precision and report the total-energy drift "
-                        "and the mixed-vs-FP64 energy gap every --every steps (no timing line)")
+                        "and the mixed-vs-FP64 energy gap every --every steps (no timing line); paper: the "
+                        "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases)")
+    p.add_argument("--paper-cases", default="main,dt,np", help="subset of main,dt,np for --mode paper")
     p.add_argument("--every", type=int, default=20)
     p.add_argument("--precisions", default="mixed,fp64")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -160,10 +162,94 @@ def drift(a):
     print(json.dumps(out))
 
 
+PAPER_T_END = 1e-8  # every case of the paper's PP study runs to 10 ns (Sec. 2.2)
+PAPER_WALL_S = 532.0  # the paper's time for its 16^3 case, 100 000 steps, 64 EPYC 9174F threads
+
+
+def run_series(sim, n_steps, every):
+    """Step n_steps (hipGraph replay) with diagnostics every `every` steps;
+    returns the wall time of the stepping alone and the per-bunch series."""
+    import torch
+    series = [[] for _ in sim.bunches]
+
+    def record():
+        for k, d in enumerate(sim.diagnostics()):
+            series[k].append((d["time"], d["emittance"][0], d["x_rms"][0], d["total"]))
+
+    record()
+    t_run, done = 0.0, 0
+    while done < n_steps:
+        k = min(every, n_steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step_batched(k, graph=True)
+        torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        done += k
+        record()
+    return t_run, series
+
+
+def paper(a):
+    """The paper's own PP runs (Sec. 2.2): the 16^3 cube lattice to 10 ns at
+    dt = 1e-13 s, the time-step sweep {1e-13 .. 1e-10} s and the macro-particle
+    sweep {4^3 .. 32^3} (one batch), with the emittance of Eq. (I) sampled
+    every 0.1 ns.  Prints one JSON line."""
+    import numpy as np
+    from paper_2502_10640_amd import workloads as wl
+    from paper_2502_10640_amd.sim import Simulation
+    out = {"mode": "paper", "t_end_s": PAPER_T_END, "sample_every_s": 1e-10, "cases": {}}
+
+    def summary(bunches, prec, dt, series, t_run, n_steps):
+        pairs = float(sum(b.n * (b.n - 1) for b in bunches)) * n_steps
+        res = {"precision": prec, "dt_s": dt, "steps": n_steps, "n_particles": [b.n for b in bunches],
+               "wall_s": t_run, "pairs_per_s": pairs / t_run, "emittance_x": [], "x_rms": []}
+        for k in range(len(bunches)):
+            ser = np.array(series[k])
+            e0 = ser[0, 3]
+            res["emittance_x"].append([float(v) for v in ser[:, 1]])
+            res["x_rms"].append([float(v) for v in ser[:, 2]])
+            res.setdefault("max_rel_energy_drift", []).append(float(np.max(np.abs(ser[:, 3] - e0)) / abs(e0)))
+        return res
+
+    cases = a.paper_cases.split(",")
+    if "main" in cases:
+        for prec in ("mixed", "fp64"):
+            b = wl.paper_cube(16)
+            n_steps = int(round(PAPER_T_END / b.dt))
+            print(f"[paper] 16^3 {prec}: {n_steps} steps", file=sys.stderr, flush=True)
+            with Simulation([b], prec) as sim:
+                t_run, ser = run_series(sim, n_steps, int(round(1e-10 / b.dt)))
+            out["cases"][f"main_{prec}"] = summary([b], prec, b.dt, ser, t_run, n_steps)
+        m, f = out["cases"]["main_mixed"], out["cases"]["main_fp64"]
+        em, ef = np.array(m["emittance_x"][0]), np.array(f["emittance_x"][0])
+        out["main_emittance_mixed_vs_fp64_max_rel"] = float(np.max(np.abs(em - ef)[1:] / np.abs(ef[1:])))
+        out["main_speedup_vs_paper_wall"] = PAPER_WALL_S / m["wall_s"]
+    if "dt" in cases:
+        for dt in (1e-12, 1e-11, 1e-10):
+            b = wl.paper_cube(16, dt=dt)
+            n_steps = int(round(PAPER_T_END / dt))
+            print(f"[paper] dt sweep dt={dt:g}: {n_steps} steps", file=sys.stderr, flush=True)
+            with Simulation([b], "mixed") as sim:
+                t_run, ser = run_series(sim, n_steps, max(1, int(round(1e-10 / dt))))
+            out["cases"][f"dt_{dt:g}"] = summary([b], "mixed", dt, ser, t_run, n_steps)
+    if "np" in cases:
+        bunches = wl.workload("paper_np_batch")
+        n_steps = int(round(PAPER_T_END / bunches[0].dt))
+        print(f"[paper] N_p sweep as one batch: {n_steps} steps", file=sys.stderr, flush=True)
+        with Simulation(bunches, "mixed") as sim:
+            t_run, ser = run_series(sim, n_steps, int(round(1e-10 / bunches[0].dt)))
+        out["cases"]["np_batch"] = summary(bunches, "mixed", bunches[0].dt, ser, t_run, n_steps)
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.mode == "drift":
         drift(a)
+        return
+    if a.mode == "paper":
+        paper(a)
         return
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)

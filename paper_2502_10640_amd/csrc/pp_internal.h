@@ -223,6 +223,7 @@ hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStrea
 hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
                       hipStream_t s);
 hipError_t launch_sym_fold(const SymFoldArgs& a, bool with_phi, hipStream_t s);
+int sym_blocks_per_cu(int i_per_lane);  // resident symmetric workgroups per CU (occupancy query)
 hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
                        int32_t groups_per_block, hipStream_t s);
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,

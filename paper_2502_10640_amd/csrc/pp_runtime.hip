@@ -269,6 +269,10 @@ pp_status build_items(pp_ctx* c) {
   const int K = c->k_eff();
   const int64_t BI = (int64_t)K * ppk::WG;
   const double wstar = std::ldexp(1.0, c->tun.chunk_pairs_log2);
+  // a bunch is split finely enough to fill the GPU on its own (the rule uses
+  // only the bunch's size and the device, so a bunch gives the same bits
+  // alone or inside a batch)
+  const int64_t fill = (int64_t)c->cus * c->tun.grid_per_cu;
 
   struct Cand { WorkItem w; double cost; };
   std::vector<Cand> cand;
@@ -279,6 +283,8 @@ pp_status build_items(pp_ctx* c) {
     const double full = (double)std::min(BI, n) * (double)n;
     int64_t nch = (int64_t)std::llround(full / wstar);
     const int64_t max_ch = (n + ppk::JT - 1) / ppk::JT;
+    const int64_t nib0 = (n + BI - 1) / BI;
+    nch = std::max(nch, (fill + nib0 - 1) / nib0);
     nch = std::max<int64_t>(1, std::min(nch, max_ch));
     int64_t per = (n + nch - 1) / nch;
     int64_t chunk_len = ((per + ppk::JT - 1) / ppk::JT) * ppk::JT;
@@ -584,24 +590,47 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   return true;
 }
 
-// Default: the symmetric schedule with the near/far split at D = U / 8 when
-// every bunch splits into at least 512 blocks, else the ordered-pair kernel.
-pp_tuning default_tuning(bool mixed, int64_t min_n) {
+// Default tiling from the bunch sizes.  The symmetric schedule (with the
+// near/far split at D = U / 8) is taken when a cost model says it is cheaper
+// than the ordered-pair kernel.  Costs in units of one ordered pair in the
+// ordered kernel, from measurements on MI355X: an off-diagonal unordered pair
+// 1.02, a diagonal-block pair 0.6, times 1.1 for 2 receivers per lane instead
+// of 4 (1 per lane measured ~2x slower and is left to the autotuner); padded
+// blocks are paid in full, and the cost is divided by the fill of the last
+// wave of workgroups (items over resident slots times the waves they need).
+pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
+  int64_t min_n = INT64_MAX;
+  double ordered = 0.0;
+  for (const auto& b : hb) {
+    min_n = std::min<int64_t>(min_n, b.n);
+    ordered += (double)b.n * (double)b.n;
+  }
   pp_tuning t{};
-  t.i_per_lane = mixed ? 2 : 1;
+  t.i_per_lane = (mixed && min_n >= 16384) ? 2 : 1;
   t.sum_tile = 64;
   t.chunk_pairs_log2 = 22;
   t.grid_per_cu = 4;
   t.graph_steps = 16;
   t.symmetric = 0;
-  if (mixed) {
-    for (int k : {4, 2, 1}) {
-      if (min_n >= (int64_t)512 * ppk::SYM_WG * k) {
-        t.symmetric = 1;
-        t.i_per_lane = k;
-        t.far_split = 3;  // per-term change at most 3.3e-6 relative
-        break;
-      }
+  if (!mixed) return t;
+  double best = ordered;
+  for (int k : {4, 2}) {
+    const double bs = (double)ppk::SYM_WG * k;
+    const double eff = k == 4 ? 1.0 : 1.1;
+    double cost = 0.0, items = 0.0;
+    for (const auto& b : hb) {
+      const double nbk = std::ceil((double)b.n / bs);
+      cost += bs * bs * (0.6 * nbk + 1.02 * nbk * (nbk - 1.0) / 2.0) * eff;
+      items += nbk * (nbk + 1.0) / 2.0;
+    }
+    const double slots = (double)cus * ppk::sym_blocks_per_cu(k);
+    const double fill = items / (slots * std::ceil(items / slots));
+    cost /= fill;
+    if (cost < best) {
+      best = cost;
+      t.symmetric = 1;
+      t.i_per_lane = k;
+      t.far_split = 3;  // per-term change at most 3.3e-6 relative
     }
   }
   return t;
@@ -748,6 +777,7 @@ pp_status autotune(pp_ctx* c) {
   for (int ts : tiles) { pp_tuning t = best; t.sum_tile = ts; if ((s = trial(t)) != PP_OK) return s; }
   const int gpc[] = {1, 2, 4, 8};
   for (int g : gpc) { pp_tuning t = best; t.grid_per_cu = g; if ((s = trial(t)) != PP_OK) return s; }
+  for (int cp : {18, 20, 22, 24}) { pp_tuning t = best; t.chunk_pairs_log2 = cp; if ((s = trial(t)) != PP_OK) return s; }
   if (c->mixed()) {
     for (int sym : {0, 1}) {
       for (int k : {1, 2, 4}) {
@@ -948,9 +978,7 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
   if ((st0 = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return fail(st0);
   PP_CREATE_HIP(ppk::launch_qprep(c->dbunch, c->bid, n_total, S.q, c->mixed() ? c->plane(6) : nullptr, c->qt64,
                                   c->stream));
-  int64_t min_n = INT64_MAX;
-  for (int b = 0; b < n_bunches; ++b) min_n = std::min<int64_t>(min_n, bunches[b].n);
-  c->tun = default_tuning(c->mixed(), min_n);
+  c->tun = default_tuning(c->mixed(), c->hb, c->cus);
   pp_status st = build_items(c);
   if (st != PP_OK) return fail(st);
 #undef PP_CREATE_HIP

@@ -379,6 +379,18 @@ hipError_t launch_sym_fold(const SymFoldArgs& a, bool with_phi, hipStream_t s) {
   return hipGetLastError();
 }
 
+int sym_blocks_per_cu(int i_per_lane) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (i_per_lane) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym_kernel<1, true, false>, SYM_WG, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym_kernel<2, true, false>, SYM_WG, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym_kernel<4, true, false>, SYM_WG, 0); break;
+    default: break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q, bool with_phi,
                       hipStream_t s) {
   if (count <= 0) return hipSuccess;

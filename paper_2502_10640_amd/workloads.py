@@ -215,6 +215,8 @@ def workload(name: str, n_override: int | None = None) -> List[Bunch]:
                          particles, 4e10 electrons, eps = 5e-4 spacing,
                          dt = 0.005/omega_p, 20 steps (1005)
     paper_cube_16        the paper's 16^3 lattice cube (Sec. 2.1), eps = 0
+    paper_np_batch       the paper's macro-particle sweep (Sec. 2.2): cubes of 4^3, 8^3,
+                         16^3 and 32^3 particles, dt = 1e-13 s, as one batch
     ``n_override`` replaces the particle count (same recipe, smaller or larger).
     """
     if name == "cold_sphere_2048":
@@ -237,11 +239,13 @@ def workload(name: str, n_override: int | None = None) -> List[Bunch]:
         return out
     if name == "paper_cube_16":
         return [paper_cube(16)]
+    if name == "paper_np_batch":
+        return [paper_cube(k) for k in (4, 8, 16, 32)]
     raise KeyError(name)
 
 
 WORKLOADS = ("cold_sphere_2048", "gaussian_65536", "cold_sphere_1m", "sweep_64", "ellipsoid_4m",
-             "paper_cube_16")
+             "paper_cube_16", "paper_np_batch")
 
 
 def concat(bunches: List[Bunch]):

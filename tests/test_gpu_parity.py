@@ -236,14 +236,23 @@ def test_push_equals_step_batched_bitwise(prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_batch_equals_separate_contexts_bitwise(prec):
+    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 0, "far_split": 0})
+
+
+def test_symmetric_far_batch_equals_separate_contexts_bitwise():
+    # the sort keys, the coordinate bound, the boxes and the fold are all per bunch
+    _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "far_split": 3})
+
+
+def _batch_equals_separate(prec, tuning):
     bunches = [wl.workload("gaussian_65536", n_override=n)[0] for n in (700, 1300, 2100)]
-    say(f"batch == separate {prec}")
-    with Sim(bunches, prec) as sim:
+    say(f"batch == separate {prec} {tuning}")
+    with Sim(bunches, prec, tuning=tuning) as sim:
         sim.push(3)
         batched = [np.concatenate([sim.host(k)[sim.bunch_slice(i)] for k in ("x", "vx", "vz")])
                    for i in range(len(bunches))]
     for i, b in enumerate(bunches):
-        with Sim([b], prec) as one:
+        with Sim([b], prec, tuning=tuning) as one:
             one.push(3)
             alone = np.concatenate([one.host(k) for k in ("x", "vx", "vz")])
         np.testing.assert_array_equal(batched[i], alone)
@@ -484,3 +493,30 @@ def test_far_split_tuning_rules():
     with Sim([b], "fp64") as sim:
         with pytest.raises(pp.PPError):
             sim.set_tuning(symmetric=1, i_per_lane=1, far_split=1)
+
+
+def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatch):
+    """PP_AUTOTUNE times candidate tilings (ordered and symmetric, with and
+    without the far split), keeps the fastest one that reproduces the field,
+    and stores it; a second context of the same shape reuses the stored one."""
+    b = wl.workload("gaussian_65536", n_override=20000)[0]
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PP_TUNE_CACHE", str(cache))
+    say(f"autotune mixed n={b.n}, cache {cache}")
+    with Sim([b], "mixed") as sim:
+        sim.step_batched(2, graph=False, autotune=True)
+        tuned = sim.tuning()
+        got = gpu_field(sim)
+        st = {k: sim.host(k) for k in ("x", "y", "z")}
+    print(f"    tuning chosen: {tuned}", flush=True)
+    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
+    check_field(got, ref, TOL["mixed"], "autotuned tiling")
+    line = cache.read_text().split()
+    assert len(line) == 8 and line[0].startswith("gfx950:")
+    assert [int(v) for v in line[1:]] == [tuned[k] for k in ("i_per_lane", "sum_tile", "chunk_pairs_log2",
+                                                               "grid_per_cu", "graph_steps", "symmetric",
+                                                               "far_split")]
+    with Sim([b], "mixed") as sim:
+        sim.step_batched(1, graph=False, autotune=True)
+        assert sim.tuning() == tuned
+    assert len(cache.read_text().splitlines()) == 1  # found in the cache: no second search
