@@ -11,6 +11,9 @@ namespace ppk {
 // particles staged in LDS per tile (one global load per thread per tile).
 constexpr int WG = 256;
 constexpr int JT = WG;
+// Smallest j-chunk of the ordered-pair work list (a partly filled tile); used
+// only where chunks of whole tiles would leave the GPU idle.
+constexpr int CHUNK_MIN = 64;
 
 // Per-bunch constants in device memory.
 //   Mixed path: positions enter the pair sum as u = (r - origin) * scale with
@@ -33,7 +36,7 @@ struct BunchDev {
   double eps2;        // FP64 path: eps^2 [m^2]
   float eps2s;        // mixed path: (eps * scale)^2
   int32_t n_chunks;   // j-chunks the bunch's sources are split into
-  int64_t chunk_len;  // sources per chunk (multiple of JT but the last)
+  int64_t chunk_len;  // sources per chunk (multiple of JT, or of CHUNK_MIN for small bunches)
   int64_t pbase;      // first partial-sum slot of the bunch
   int64_t cstart;     // spatial sort: first position of the bunch in the compacted key array
   int32_t gbase;      // spatial sort: first 64-particle group box of the bunch
@@ -54,6 +57,7 @@ struct PairArgs {
   const WorkItem* items;
   int32_t n_items;
   int32_t* counter;        // persistent-kernel work counter (zeroed by the pack kernel)
+  int32_t direct;          // 1: one workgroup per item (item = blockIdx.x), no counter
   // mixed-path source mirror, FP32 SoA over all particles
   const float* xh; const float* yh; const float* zh;
   const float* xl; const float* yl; const float* zl;
@@ -161,7 +165,9 @@ struct PackArgs {
 enum FinalMode : int32_t {
   FIN_FIELD = 0,   // write E (and phi) to output arrays
   FIN_ACCEL = 1,   // a = (q/m) E
-  FIN_KICK = 2     // a' = (q/m) E; v += (a + a') dt / 2; a = a'
+  FIN_KICK = 2,    // a' = (q/m) E; v += (a + a') dt / 2; a = a'
+  FIN_KICK_DRIFT = 3  // FIN_KICK, then the next step's drift and mirror pack
+                      // (the pack kernel's work, same arithmetic)
 };
 
 struct FinalArgs {
@@ -178,6 +184,10 @@ struct FinalArgs {
   double *ex, *ey, *ez, *phi;   // FIN_FIELD outputs (phi may be null)
   int32_t sym;                  // partials are the symmetric accumulators
   const int32_t* rank;          // symmetric accumulators in sorted order: slot = rank[i]
+  // FIN_KICK_DRIFT: positions, mixed mirror and the pair kernel's work counter
+  double *x, *y, *z;
+  float *xh, *yh, *zh, *xl, *yl, *zl;
+  int32_t* counter;
 };
 
 // Diagnostics: per-bunch reduction record in device memory (doubles).

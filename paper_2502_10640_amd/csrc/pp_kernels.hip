@@ -83,11 +83,18 @@ void pair_mixed_kernel(PairArgs a, int32_t sum_tile) {
   __shared__ float4 s_lo[JT];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  for (;;) {
-    __syncthreads();  // previous item done with s_item and the tile
-    if (tid == 0) s_item = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int it = s_item;
+  for (int pass = 0;; ++pass) {
+    int it;
+    if (a.direct) {
+      // one workgroup per item, in work-list order: no counter
+      if (pass > 0) break;
+      it = blockIdx.x;
+    } else {
+      __syncthreads();  // previous item done with s_item and the tile
+      if (tid == 0) s_item = atomicAdd(a.counter, 1);
+      __syncthreads();
+      it = s_item;
+    }
     if (it >= a.n_items) break;
     const WorkItem w = a.items[it];
     const BunchDev& B = a.bunches[w.b];
@@ -214,11 +221,17 @@ __global__ __launch_bounds__(WG) void pair_fp64_kernel(PairArgs a, int32_t sum_t
   __shared__ double4 s_j[JT];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) s_item = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int it = s_item;
+  for (int pass = 0;; ++pass) {
+    int it;
+    if (a.direct) {
+      if (pass > 0) break;
+      it = blockIdx.x;
+    } else {
+      __syncthreads();
+      if (tid == 0) s_item = atomicAdd(a.counter, 1);
+      __syncthreads();
+      it = s_item;
+    }
     if (it >= a.n_items) break;
     const WorkItem w = a.items[it];
     const BunchDev& B = a.bunches[w.b];
@@ -295,6 +308,19 @@ __device__ __forceinline__ double drift1(double r, double v, double acc, double 
   return r + v * dt + acc * dt * dt / 2.0;
 }
 
+// mirror of one particle: u = (r - origin) * scale, hi = fl32(u), lo = fl32(u - hi)
+__device__ __forceinline__ void mirror1(const BunchDev& B, int64_t i, double x, double y, double z, float* xh,
+                                        float* yh, float* zh, float* xl, float* yl, float* zl) {
+  const double ux = (x - B.origin[0]) * B.scale;
+  const double uy = (y - B.origin[1]) * B.scale;
+  const double uz = (z - B.origin[2]) * B.scale;
+  const float hx = (float)ux, hy = (float)uy, hz = (float)uz;
+  xh[i] = hx; yh[i] = hy; zh[i] = hz;
+  xl[i] = (float)(ux - (double)hx);
+  yl[i] = (float)(uy - (double)hy);
+  zl[i] = (float)(uz - (double)hz);
+}
+
 template <bool DRIFT, bool MIXED>
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,16 +337,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     z = drift1(z, a.vz[i], a.az[i], dt);
     a.x[i] = x; a.y[i] = y; a.z[i] = z;
   }
-  if (MIXED) {
-    const double ux = (x - B.origin[0]) * B.scale;
-    const double uy = (y - B.origin[1]) * B.scale;
-    const double uz = (z - B.origin[2]) * B.scale;
-    const float hx = (float)ux, hy = (float)uy, hz = (float)uz;
-    a.xh[i] = hx; a.yh[i] = hy; a.zh[i] = hz;
-    a.xl[i] = (float)(ux - (double)hx);
-    a.yl[i] = (float)(uy - (double)hy);
-    a.zl[i] = (float)(uz - (double)hz);
-  }
+  if (MIXED) mirror1(B, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,9 +349,19 @@ __device__ __forceinline__ double kick1(double v, double a0, double a1, double d
   return v + (a0 + a1) * dt / 2.0;
 }
 
-template <bool MIXED, int MODE>
+// L lanes per particle.  The ordered-pair path uses L = FIN_LANES: lane t adds
+// chunks t, t + L, ... in order, then an xor butterfly over the L lanes (every
+// lane ends with the same bits, a + b == b + a); the rule depends only on the
+// bunch's chunk count.  The symmetric path uses L = 1.
+constexpr int FIN_LANES = 8;
+
+template <bool MIXED, int MODE, int L>
 __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (MODE == FIN_KICK_DRIFT && gt == 0) *a.counter = 0;  // for the next pair kernel on the stream
+  const int t = (int)(gt % L);
+  const int64_t i = gt / L;
+  // the L lanes of a particle take every branch below together
   if (i >= a.n_total) return;
   const int b = a.bid[i];
   if (b < 0) return;
@@ -352,7 +379,9 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
     ez = ((double)f[2 * P + r] + (double)f[5 * P + r]) + ((double)f[8 * P + r] + (double)f[11 * P + r]);
     if (want_phi) ph = ((double)f[12 * P + r] + (double)f[13 * P + r]) + ((double)f[14 * P + r] + (double)f[15 * P + r]);
   }
-  for (int c = 0; c < ((MIXED && a.sym) ? 0 : B.n_chunks); ++c) {
+  // this lane's chunks in chunk order
+#pragma unroll 4
+  for (int c = t; c < ((MIXED && a.sym) ? 0 : B.n_chunks); c += L) {
     const int64_t s = B.pbase + (int64_t)c * B.n + li;
     if (MIXED) {
       ex += (double)a.pf[0 * a.P + s] + (double)a.pf[3 * a.P + s];
@@ -366,6 +395,16 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
       if (want_phi) ph += a.pd[6 * a.P + s] + a.pd[7 * a.P + s];
     }
   }
+  if (L > 1) {
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1) {
+      ex += __shfl_xor(ex, m, L);
+      ey += __shfl_xor(ey, m, L);
+      ez += __shfl_xor(ez, m, L);
+      if (want_phi) ph += __shfl_xor(ph, m, L);
+    }
+    if (t != 0) return;
+  }
   ex *= B.kE; ey *= B.kE; ez *= B.kE;
   if (MODE == FIN_FIELD) {
     if (a.ex) { a.ex[i] = ex; a.ey[i] = ey; a.ez[i] = ez; }
@@ -374,11 +413,20 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   }
   const double qm = a.q[i] / a.m[i];
   const double nax = ex * qm, nay = ey * qm, naz = ez * qm;
-  if (MODE == FIN_KICK) {
+  if (MODE == FIN_KICK || MODE == FIN_KICK_DRIFT) {
     const double dt = B.dt;
-    a.vx[i] = kick1(a.vx[i], a.ax[i], nax, dt);
-    a.vy[i] = kick1(a.vy[i], a.ay[i], nay, dt);
-    a.vz[i] = kick1(a.vz[i], a.az[i], naz, dt);
+    const double vx = kick1(a.vx[i], a.ax[i], nax, dt);
+    const double vy = kick1(a.vy[i], a.ay[i], nay, dt);
+    const double vz = kick1(a.vz[i], a.az[i], naz, dt);
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    if (MODE == FIN_KICK_DRIFT) {
+      // the next step's drift (Eq. (G)) with the velocity and acceleration just stored
+      const double x = drift1(a.x[i], vx, nax, dt);
+      const double y = drift1(a.y[i], vy, nay, dt);
+      const double z = drift1(a.z[i], vz, naz, dt);
+      a.x[i] = x; a.y[i] = y; a.z[i] = z;
+      if (MIXED) mirror1(B, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
+    }
   }
   a.ax[i] = nax; a.ay[i] = nay; a.az[i] = naz;
 }
@@ -655,21 +703,29 @@ hipError_t launch_pack(const PackArgs& a, bool drift, bool mixed, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s) {
-  const unsigned nb = blocks_for(a.n_total, 256);
+template <int L>
+hipError_t go_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s) {
+  const unsigned nb = blocks_for(a.n_total * L, 256);
   if (nb == 0) return hipSuccess;
-#define PP_FIN(M, MD) hipLaunchKernelGGL((final_kernel<M, MD>), dim3(nb), dim3(256), 0, s, a)
+#define PP_FIN(M, MD) hipLaunchKernelGGL((final_kernel<M, MD, L>), dim3(nb), dim3(256), 0, s, a)
   if (mixed) {
     if (mode == FIN_FIELD) PP_FIN(true, FIN_FIELD);
     else if (mode == FIN_ACCEL) PP_FIN(true, FIN_ACCEL);
-    else PP_FIN(true, FIN_KICK);
+    else if (mode == FIN_KICK) PP_FIN(true, FIN_KICK);
+    else PP_FIN(true, FIN_KICK_DRIFT);
   } else {
     if (mode == FIN_FIELD) PP_FIN(false, FIN_FIELD);
     else if (mode == FIN_ACCEL) PP_FIN(false, FIN_ACCEL);
-    else PP_FIN(false, FIN_KICK);
+    else if (mode == FIN_KICK) PP_FIN(false, FIN_KICK);
+    else PP_FIN(false, FIN_KICK_DRIFT);
   }
 #undef PP_FIN
   return hipGetLastError();
+}
+
+hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s) {
+  if (mixed && a.sym) return go_final<1>(a, mixed, mode, s);
+  return go_final<FIN_LANES>(a, mixed, mode, s);
 }
 
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q, float* qt,

@@ -281,13 +281,16 @@ pp_status build_items(pp_ctx* c) {
   for (int b = 0; b < c->nb; ++b) {
     const int64_t n = c->hb[b].n;
     const double full = (double)std::min(BI, n) * (double)n;
+    // chunks are whole LDS tiles (JT sources) where that still fills the GPU,
+    // else multiples of CHUNK_MIN sources (a partly filled tile)
     int64_t nch = (int64_t)std::llround(full / wstar);
-    const int64_t max_ch = (n + ppk::JT - 1) / ppk::JT;
+    const int64_t max_ch = (n + ppk::CHUNK_MIN - 1) / ppk::CHUNK_MIN;
     const int64_t nib0 = (n + BI - 1) / BI;
     nch = std::max(nch, (fill + nib0 - 1) / nib0);
     nch = std::max<int64_t>(1, std::min(nch, max_ch));
-    int64_t per = (n + nch - 1) / nch;
-    int64_t chunk_len = ((per + ppk::JT - 1) / ppk::JT) * ppk::JT;
+    const int64_t per = (n + nch - 1) / nch;
+    const int64_t gran = per >= ppk::JT ? ppk::JT : ppk::CHUNK_MIN;
+    const int64_t chunk_len = ((per + gran - 1) / gran) * gran;
     nch = (n + chunk_len - 1) / chunk_len;
     BunchDev& B = c->hbd[b];
     B.n_chunks = (int32_t)nch;
@@ -354,12 +357,18 @@ pp_status build_items(pp_ctx* c) {
 // ---------------------------------------------------------------------------
 // Kernel argument blocks.
 // ---------------------------------------------------------------------------
+// Short work lists run one workgroup per item (the dispatcher hands them out
+// in work-list order); long ones use the persistent grid and its counter, whose
+// one atomic per item would serialise a list of many tiny items.
+bool direct_items(const pp_ctx* c) { return c->n_items <= 65536; }
+
 ppk::PairArgs pair_args(pp_ctx* c) {
   ppk::PairArgs a{};
   a.bunches = c->dbunch;
   a.items = c->items;
   a.n_items = c->n_items;
   a.counter = c->counter;
+  a.direct = direct_items(c) ? 1 : 0;
   if (c->mixed()) {
     a.xh = c->plane(0); a.yh = c->plane(1); a.zh = c->plane(2);
     a.xl = c->plane(3); a.yl = c->plane(4); a.zl = c->plane(5);
@@ -400,6 +409,12 @@ ppk::FinalArgs final_args(pp_ctx* c) {
   a.P = c->sym() ? c->n_total : c->P;
   a.sym = c->sym() ? 1 : 0;
   a.rank = c->far() ? c->rank : nullptr;
+  a.x = c->st.x; a.y = c->st.y; a.z = c->st.z;
+  if (c->mixed()) {
+    a.xh = c->plane(0); a.yh = c->plane(1); a.zh = c->plane(2);
+    a.xl = c->plane(3); a.yl = c->plane(4); a.zl = c->plane(5);
+  }
+  a.counter = c->counter;
   a.q = c->st.q;
   a.m = c->st.m;
   a.vx = c->st.vx; a.vy = c->st.vy; a.vz = c->st.vz;
@@ -408,6 +423,7 @@ ppk::FinalArgs final_args(pp_ctx* c) {
 }
 
 int grid_size(pp_ctx* c) {
+  if (direct_items(c)) return c->n_items;
   const int64_t g = (int64_t)c->cus * c->tun.grid_per_cu;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, c->n_items));
 }
@@ -533,11 +549,20 @@ pp_status ensure_accel(pp_ctx* c) {
   return PP_OK;
 }
 
-pp_status enqueue_step(pp_ctx* c, hipStream_t s, bool timed) {
+// n >= 1 Velocity Verlet steps on stream s: the first drift, then per step the
+// pair stage and the kick; the kick of every step but the last also does the
+// next step's drift and mirror pack (2n + 1 kernels of the ordered path instead
+// of 3n, with the same arithmetic).
+pp_status enqueue_steps(pp_ctx* c, int64_t n, hipStream_t s, bool timed) {
   pp_status r;
+  if (n <= 0) return PP_OK;
   if ((r = enqueue_pack(c, true, s)) != PP_OK) return r;
-  if ((r = enqueue_pair(c, false, s, timed)) != PP_OK) return r;
-  return enqueue_final(c, ppk::FIN_KICK, nullptr, nullptr, nullptr, nullptr, s);
+  for (int64_t k = 0; k < n; ++k) {
+    if ((r = enqueue_pair(c, false, s, timed)) != PP_OK) return r;
+    const ppk::FinalMode m = k + 1 < n ? ppk::FIN_KICK_DRIFT : ppk::FIN_KICK;
+    if ((r = enqueue_final(c, m, nullptr, nullptr, nullptr, nullptr, s)) != PP_OK) return r;
+  }
+  return PP_OK;
 }
 
 void drop_graph(pp_ctx* c) {
@@ -549,7 +574,7 @@ pp_status capture_graph(pp_ctx* c, int64_t steps) {
   drop_graph(c);
   PP_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
   pp_status st = PP_OK;
-  for (int64_t k = 0; k < steps && st == PP_OK; ++k) st = enqueue_step(c, c->cap, false);
+  st = enqueue_steps(c, steps, c->cap, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (st != PP_OK) {
@@ -1000,10 +1025,8 @@ pp_status pp_push(pp_ctx* c, int64_t n_steps) {
   if ((s = usable(c)) != PP_OK) return s;
   if (n_steps < 0) return set_err(c, PP_ERR_INVALID_ARG, "n_steps < 0");
   if ((s = ensure_accel(c)) != PP_OK) return s;
-  for (int64_t k = 0; k < n_steps; ++k) {
-    if ((s = enqueue_step(c, c->stream, c->prof)) != PP_OK) return s;
-    ++c->step;
-  }
+  if ((s = enqueue_steps(c, n_steps, c->stream, c->prof)) != PP_OK) return s;
+  c->step += n_steps;
   return PP_OK;
 }
 
@@ -1027,10 +1050,8 @@ pp_status pp_step_batched(pp_ctx* c, int64_t n_steps, uint32_t flags) {
       c->step += c->graph.steps;
     }
   }
-  for (; left > 0; --left) {
-    if ((s = enqueue_step(c, c->stream, c->prof)) != PP_OK) return s;
-    ++c->step;
-  }
+  if ((s = enqueue_steps(c, left, c->stream, c->prof)) != PP_OK) return s;
+  c->step += left;
   if (flags & PP_CHECK) return check_finite(c);
   return PP_OK;
 }
