@@ -520,3 +520,48 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
         sim.step_batched(1, graph=False, autotune=True)
         assert sim.tuning() == tuned
     assert len(cache.read_text().splitlines()) == 1  # found in the cache: no second search
+
+
+# ---------------------------------------------------------------------------
+# the other benchmark workloads at full size, default tilings (as bench.py runs them)
+# ---------------------------------------------------------------------------
+
+def test_full_size_parity_gaussian_65536(orc):
+    b = wl.workload("gaussian_65536")[0]
+    say(f"full size parity gaussian_65536 mixed n={b.n} (every receiver)")
+    with Sim([b], "mixed") as sim:
+        print(f"    tuning {sim.tuning()}", flush=True)
+        got = gpu_field(sim)
+    check_field(got, oracle_field(orc, b), TOL["mixed"], "gaussian_65536/mixed")
+
+
+def test_full_size_sampled_parity_ellipsoid_4m(orc):
+    b = wl.workload("ellipsoid_4m")[0]
+    rng = np.random.default_rng(98)
+    recv = np.sort(rng.choice(b.n, 384, replace=False))
+    say(f"full size sampled parity ellipsoid_4m mixed n={b.n}")
+    with Sim([b], "mixed") as sim:
+        print(f"    tuning {sim.tuning()}", flush=True)
+        got = gpu_field(sim, sl=recv)
+    check_field(got, oracle_field(orc, b, recv=recv), TOL["mixed"], "ellipsoid_4m/mixed sampled")
+
+
+def test_full_size_sampled_parity_sweep_64(orc):
+    bunches = wl.workload("sweep_64")
+    rng = np.random.default_rng(97)
+    say(f"full size sampled parity sweep_64 mixed: {len(bunches)} bunches, {sum(b.n for b in bunches)} particles")
+    with Sim(bunches, "mixed") as sim:
+        print(f"    tuning {sim.tuning()}", flush=True)
+        full = gpu_field(sim)
+        slices = [sim.bunch_slice(k) for k in range(len(bunches))]
+    worst = (0.0, 0.0)
+    for k, b in enumerate(bunches):
+        recv = np.sort(rng.choice(b.n, 16, replace=False))
+        got = {key: v[slices[k]][recv] for key, v in full.items()}
+        ref = oracle_field(orc, b, recv=recv)
+        G, R = vec(got), vec(ref)
+        e = (l2_rel(G, R), cond_max(G, R, ref["amag"]))
+        worst = (max(worst[0], e[0]), max(worst[1], e[1]))
+        assert e[0] <= TOL["mixed"] and e[1] <= TOL["mixed"], (k, b.n, e)
+        assert l2_rel(got["phi"], ref["phi"]) <= TOL["mixed"], k
+    print(f"    sweep_64 worst over bunches: l2={worst[0]:.3e} cond_max={worst[1]:.3e}", flush=True)
