@@ -220,7 +220,10 @@ pp_status build_sym(pp_ctx* c) {
   if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
   const int64_t rounds = maxr + 1;
   const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * sizeof(float);
-  const int64_t band = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
+  // the fewest bands that fit, of equal size (no short last band leaving the GPU half idle)
+  const int64_t band_max = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
+  const int64_t n_bands = (rounds + band_max - 1) / band_max;
+  const int64_t band = (rounds + n_bands - 1) / n_bands;
   c->bands.clear();
   for (int64_t r0 = 0; r0 < rounds; r0 += band) {
     const int64_t r1 = std::min(rounds, r0 + band);
