@@ -134,13 +134,14 @@ typedef struct {
                             512 i_per_lane particles); 0 evaluates every ordered
                             pair in the persistent kernel                       */
   int32_t far_split;     /* symmetric only: 0 keeps the hi/lo separations of
-                            Sec. 3 for every pair; f in 1..8 orders each bunch
+                            Sec. 3 for every pair; f in 1..4 orders each bunch
                             along a Morton curve every evaluation and uses plain
                             FP32 separations for a 64-source group whose box is
                             farther than D = U 2^-f from the receiver block's
                             box (U: largest scaled coordinate of the bunch).
                             Each such term then differs from the hi/lo term by
-                            at most 2 sqrt(3) 2^-23 2^f relative.               */
+                            at most 2 sqrt(3) 2^-23 2^f relative (6.6e-6 at
+                            f = 4, inside the mixed tolerance).                 */
 } pp_tuning;
 
 /* Create a context over n_bunches bunches of a state of n_total particles.

@@ -614,7 +614,8 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
   if (t.symmetric != 0 && t.symmetric != 1) return false;
   if (t.symmetric && (!mixed || k == 8)) return false;
-  if (t.far_split < 0 || t.far_split > 8 || (t.far_split > 0 && !t.symmetric)) return false;
+  // far_split <= 4 keeps the per-term bound 2 sqrt(3) 2^-23 2^f at 6.6e-6, inside the mixed tolerance
+  if (t.far_split < 0 || t.far_split > 4 || (t.far_split > 0 && !t.symmetric)) return false;
   return true;
 }
 

@@ -240,6 +240,17 @@ __device__ __forceinline__ int bunch_of_group(const BunchDev* bunches, int nb, i
   return lo;
 }
 
+// bunch of symmetric block q (blocks are numbered bunch by bunch)
+__device__ __forceinline__ int bunch_of_block(const BunchDev* bunches, int nb, int q) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bunches[mid].bbase <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // one wavefront per group of 64 sorted particles: box of the FP32 high parts
 __global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_total) {
   const int g = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -269,9 +280,7 @@ __global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_
 __global__ __launch_bounds__(256) void bbox_kernel(SortArgs a, int32_t n_blocks_total, int32_t groups_per_block) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_blocks_total) return;
-  int b = 0;
-  while (b + 1 < a.nb && a.bunches[b + 1].bbase <= q) ++b;
-  const BunchDev& B = a.bunches[b];
+  const BunchDev& B = a.bunches[bunch_of_block(a.bunches, a.nb, q)];
   const int ng = (int)((B.n + 63) / 64);
   const int g0 = (q - B.bbase) * groups_per_block;
   const int g1 = min(ng, g0 + groups_per_block);

@@ -485,7 +485,7 @@ def test_far_split_tuning_rules():
     b = wl.workload("cold_sphere_2048", n_override=64)[0]
     say("far split tuning validation")
     with Sim([b], "mixed") as sim:
-        for bad in ({"symmetric": 0, "far_split": 2}, {"symmetric": 1, "i_per_lane": 1, "far_split": 9},
+        for bad in ({"symmetric": 0, "far_split": 2}, {"symmetric": 1, "i_per_lane": 1, "far_split": 5},
                     {"symmetric": 1, "i_per_lane": 1, "far_split": -1}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
