@@ -68,8 +68,8 @@ typedef enum { PP_FP64 = 0, PP_MIXED = 1 } pp_precision;
  * left untouched).  Sec. 2.1: all macro-particles of a bunch share one
  * weight w (Q = q w, M = m w). */
 typedef struct {
-  int64_t offset;   /* >= 0                                   */
-  int64_t n;        /* >= 1 particles                          */
+  int64_t offset;   /* >= 0; bunches in increasing, disjoint order */
+  int64_t n;        /* 1 <= n < 2^30 particles                 */
   double weight;    /* w > 0, real particles per macro-particle */
   double softening; /* eps >= 0 [m]; 0 is the bare Eq. (B)     */
   double dt;        /* Velocity Verlet step > 0 [s]            */
@@ -154,7 +154,7 @@ typedef struct {
  *   prec        PP_FP64 or PP_MIXED
  *   hip_stream  hipStream_t every call enqueues on; NULL is the device's
  *               legacy default stream (ordered with all blocking streams)
- * Errors: PP_ERR_INVALID_ARG (null pointers, n < 1, bad offsets, w <= 0,
+ * Errors: PP_ERR_INVALID_ARG (null pointers, n < 1 or n >= 2^30, bad offsets, w <= 0,
  * eps < 0, dt <= 0, non-finite parameters, m <= 0 or non-finite q/m on the
  * device), PP_ERR_OUT_OF_MEMORY, PP_ERR_DEVICE.  On error *out is NULL and
  * pp_last_error(NULL) holds the message. */

@@ -875,7 +875,7 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
       return set_err(nullptr, PP_ERR_INVALID_ARG, buf);
     }
     if (B.n > (int64_t)INT32_MAX / 2) {
-      std::snprintf(buf, sizeof buf, "bunch %d: more than 2^30 particles", b);
+      std::snprintf(buf, sizeof buf, "bunch %d: 2^30 or more particles (local indices are 32-bit)", b);
       return set_err(nullptr, PP_ERR_INVALID_ARG, buf);
     }
     if (!finite_pos(B.weight) || !finite_pos(B.dt) || !std::isfinite(B.softening) || B.softening < 0.0) {

@@ -55,6 +55,7 @@ FAKE = [0x1000 * (k + 1) for k in range(8)]   # never dereferenced: validation f
     ([(0, 10, 1.0, -1.0, 1e-15)], 10, FAKE, pp.PP_MIXED, "softening >= 0"),
     ([(0, 10, 1.0, 0.0, 0.0)], 10, FAKE, pp.PP_MIXED, "dt > 0"),
     ([(0, 10, 1.0, float("nan"), 1e-15)], 10, FAKE, pp.PP_MIXED, "finite"),
+    ([(0, 2 ** 30, 1.0, 0.0, 1e-15)], 2 ** 30, FAKE, pp.PP_MIXED, "2^30 or more"),
     ([(0, 10, float("inf"), 0.0, 1e-15)], 10, FAKE, pp.PP_MIXED, "finite"),
     ([(0, 10, 1.0, 0.0, 1e-15)], 0, FAKE, pp.PP_MIXED, "n_total"),
 ])
