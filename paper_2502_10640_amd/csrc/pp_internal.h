@@ -40,7 +40,7 @@ struct BunchDev {
   int64_t pbase;      // first partial-sum slot of the bunch
   int64_t cstart;     // spatial sort: first position of the bunch in the compacted key array
   int32_t gbase;      // spatial sort: first 64-particle group box of the bunch
-  int32_t bbase;      // spatial sort: first symmetric-block box of the bunch
+  int32_t bbase;      // symmetric schedule: first block of the bunch over all bunches
 };
 
 // One unit of pair work: receivers [i0, i0 + i_per_lane * WG) of bunch b
@@ -109,11 +109,10 @@ struct SymArgs {
   int32_t r0;
   int32_t nbt;             // blocks over all bunches
   // near/far split (needs the spatial sort): a source group whose box is
-  // farther than near_frac * U from the receiver block's box uses plain FP32
+  // farther than near_frac * U from a wavefront's receiver box uses plain FP32
   // separations; near_frac = 0 keeps hi/lo separations everywhere
   float near_frac;
   const float* gbox;       // [group][6]: min xyz, max xyz of the FP32 high parts
-  const float* bbox;       // [block][6]
   const uint32_t* ubits;   // per-bunch bound U on |scaled coordinate| (float bits)
 };
 
@@ -148,7 +147,6 @@ struct SortArgs {
   uint32_t* dtot;          // 256 digit totals
   int32_t* rank;           // sorted position of each particle
   float* gbox;
-  float* bbox;
 };
 
 struct PackArgs {
@@ -234,8 +232,7 @@ hipError_t launch_sym(const SymArgs& a, int32_t first, int32_t count, int i_per_
                       hipStream_t s);
 hipError_t launch_sym_fold(const SymFoldArgs& a, bool with_phi, hipStream_t s);
 int sym_blocks_per_cu(int i_per_lane);  // resident symmetric workgroups per CU (occupancy query)
-hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
-                       int32_t groups_per_block, hipStream_t s);
+hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, hipStream_t s);
 hipError_t launch_qprep(const BunchDev* bunches, const int32_t* bid, int64_t n_total, const double* q,
                         float* qt, double* qt64, hipStream_t s);
 hipError_t launch_minmax(const BunchDev* bunches, int32_t n_bunches, const double* x, const double* y,

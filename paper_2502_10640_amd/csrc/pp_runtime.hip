@@ -85,9 +85,8 @@ struct pp_ctx {
   int32_t* rank = nullptr;         // sorted slot of each particle
   uint32_t* ubits = nullptr;       // per-bunch coordinate bound
   float* gbox = nullptr;           // 6 x 64-particle groups
-  float* bbox = nullptr;           // 6 x symmetric blocks (sized for i_per_lane 1)
   int64_t n_in = 0;                // particles inside bunches
-  int32_t n_groups = 0, n_blocks = 0, n_blocks_max = 0;
+  int32_t n_groups = 0, n_blocks = 0;
   void* hpin = nullptr;        // pinned host staging for every host<->device copy
   size_t hpin_bytes = 0;
 
@@ -258,7 +257,6 @@ pp_status build_sym(pp_ctx* c) {
     PP_HIP(c, dalloc(&c->rank, n));
     PP_HIP(c, dalloc(&c->ubits, (size_t)c->nb));
     PP_HIP(c, dalloc(&c->gbox, 6 * (size_t)c->n_groups));
-    PP_HIP(c, dalloc(&c->bbox, 6 * (size_t)c->n_blocks_max));
   }
   return h2d(c, c->sitems, items.data(), items.size() * sizeof(ppk::SymItem));
 }
@@ -280,7 +278,7 @@ pp_status build_items(pp_ctx* c) {
   struct Cand { WorkItem w; double cost; };
   std::vector<Cand> cand;
   int64_t pbase = 0;
-  int64_t cbase = 0, gbase = 0, bbase = 0, bmax = 0;
+  int64_t cbase = 0, gbase = 0, bbase = 0;
   for (int b = 0; b < c->nb; ++b) {
     const int64_t n = c->hb[b].n;
     const double full = (double)std::min(BI, n) * (double)n;
@@ -310,7 +308,6 @@ pp_status build_items(pp_ctx* c) {
     cbase += n;
     gbase += (n + 63) / 64;
     bbase += (n + bs - 1) / bs;
-    bmax += (n + ppk::SYM_WG - 1) / ppk::SYM_WG;
     const int64_t nib = (n + BI - 1) / BI;
     for (int64_t ib = 0; ib < nib; ++ib) {
       for (int64_t ch = 0; ch < nch; ++ch) {
@@ -326,7 +323,6 @@ pp_status build_items(pp_ctx* c) {
   c->n_in = cbase;
   c->n_groups = (int32_t)gbase;
   c->n_blocks = (int32_t)bbase;
-  c->n_blocks_max = (int32_t)bmax;
   std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) { return x.cost > y.cost; });
   if (cand.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "work list too long");
   std::vector<WorkItem> items(cand.size());
@@ -496,16 +492,14 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
       }
       so.rank = c->rank;
       so.gbox = c->gbox;
-      so.bbox = c->bbox;
       int bunch_bits = 0;
       while ((int64_t(1) << bunch_bits) < c->nb) ++bunch_bits;
-      PP_HIP(c, ppk::launch_sort(so, 30 + bunch_bits, c->n_groups, c->n_blocks, 8 * c->tun.i_per_lane, s));
+      PP_HIP(c, ppk::launch_sort(so, 30 + bunch_bits, c->n_groups, s));
       sa.xh = sp[0]; sa.yh = sp[1]; sa.zh = sp[2];
       sa.xl = sp[3]; sa.yl = sp[4]; sa.zl = sp[5];
       sa.qt = sp[6];
       sa.near_frac = std::ldexp(1.0f, -c->tun.far_split);
       sa.gbox = c->gbox;
-      sa.bbox = c->bbox;
       sa.ubits = c->ubits;
     }
     ppk::SymFoldArgs fa{};
@@ -836,7 +830,7 @@ void free_all(pp_ctx* c) {
   auto f = [](void* p) { if (p) hipFree(p); };
   f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
   f(c->items); f(c->sitems); f(c->acc); f(c->slot);
-  f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->bbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
+  f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
   if (c->hpin) hipHostFree(c->hpin);
   for (auto& e : c->ev_pool) hipEventDestroy(e);
   for (auto& p : c->ev_used) { hipEventDestroy(p.first); hipEventDestroy(p.second); }

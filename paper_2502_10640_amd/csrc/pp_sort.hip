@@ -4,7 +4,7 @@
 // Every step the particles of each bunch are ordered along a Morton curve of
 // their (scaled, FP32 high part) positions, so that a block of consecutive
 // particles is compact in space.  Source groups of 64 whose bounding box lies
-// farther than D from a receiver block's box can then use plain FP32
+// farther than D from a wavefront's receiver box can then use plain FP32
 // separations (hi_i - hi_j): the rounding of the positions to FP32 changes a
 // pair term by at most 2 sqrt(3) 2^-23 U / D relative (U bounds every scaled
 // coordinate of the bunch), while closer groups keep the hi/lo separations.
@@ -240,17 +240,6 @@ __device__ __forceinline__ int bunch_of_group(const BunchDev* bunches, int nb, i
   return lo;
 }
 
-// bunch of symmetric block q (blocks are numbered bunch by bunch)
-__device__ __forceinline__ int bunch_of_block(const BunchDev* bunches, int nb, int q) {
-  int lo = 0, hi = nb - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (bunches[mid].bbase <= q) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // one wavefront per group of 64 sorted particles: box of the FP32 high parts
 __global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_total) {
   const int g = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -276,28 +265,11 @@ __global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_
   if (l < 6) a.gbox[(int64_t)g * 6 + l] = v;
 }
 
-// one thread per symmetric block: union of its groups' boxes
-__global__ __launch_bounds__(256) void bbox_kernel(SortArgs a, int32_t n_blocks_total, int32_t groups_per_block) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_blocks_total) return;
-  const BunchDev& B = a.bunches[bunch_of_block(a.bunches, a.nb, q)];
-  const int ng = (int)((B.n + 63) / 64);
-  const int g0 = (q - B.bbase) * groups_per_block;
-  const int g1 = min(ng, g0 + groups_per_block);
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int g = g0; g < g1; ++g) {
-    const float* bx = a.gbox + (int64_t)(B.gbase + g) * 6;
-    for (int c = 0; c < 3; ++c) { lo[c] = fminf(lo[c], bx[c]); hi[c] = fmaxf(hi[c], bx[3 + c]); }
-  }
-  for (int c = 0; c < 3; ++c) { a.bbox[(int64_t)q * 6 + c] = lo[c]; a.bbox[(int64_t)q * 6 + 3 + c] = hi[c]; }
-}
-
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, int32_t n_blocks_total,
-                       int32_t groups_per_block, hipStream_t s) {
+hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, hipStream_t s) {
   hipLaunchKernelGGL(bound_zero_kernel, dim3(nblk(a.nb, 256)), dim3(256), 0, s, a.ubits, a.nb);
   hipLaunchKernelGGL(bound_kernel, dim3(nblk(a.n_total, 256 * BOUND_PER)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a);
@@ -322,8 +294,6 @@ hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, 
   hipLaunchKernelGGL(gather_kernel, dim3(nblk(a.n_in, 256)), dim3(256), 0, s, g);
   hipLaunchKernelGGL(gbox_kernel, dim3(nblk((int64_t)n_groups_total * 64, 256)), dim3(256), 0, s, g,
                      n_groups_total);
-  hipLaunchKernelGGL(bbox_kernel, dim3(nblk(n_blocks_total, 256)), dim3(256), 0, s, g, n_blocks_total,
-                     groups_per_block);
   return hipGetLastError();
 }
 

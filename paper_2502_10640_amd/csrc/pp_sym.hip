@@ -155,14 +155,25 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
   float* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
   float* sslot = a.slot + ((rho * a.nbt + B.bbase + it.J) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
 
-  // near/far split: receiver block box and threshold (uniform over the item)
+  // near/far split: this wavefront's receiver box (the union of the boxes of
+  // its K groups of 64 sorted receivers) and the threshold; the far/near
+  // choice is uniform over the wavefront and may differ between wavefronts
   const bool split = !DIAG && a.near_frac > 0.f;
-  float ib[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float ib[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   float dfar2 = 0.f;
   if (split) {
-    const float* bx = a.bbox + (int64_t)(B.bbase + it.I) * 6;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) ib[c] = bx[c];
+    for (int k = 0; k < K; ++k) {
+      const int gl = ibase / 64 + w * K + k;  // group of the bunch
+      if (gl * 64 < n) {
+        const float* gx = a.gbox + (int64_t)(B.gbase + gl) * 6;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ib[c] = fminf(ib[c], gx[c]);
+          ib[3 + c] = fmaxf(ib[3 + c], gx[3 + c]);
+        }
+      }
+    }
     const float dfar = a.near_frac * __uint_as_float(a.ubits[it.b]);
     dfar2 = dfar * dfar;
   }
@@ -214,8 +225,8 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     float Sj[4] = {0.f, 0.f, 0.f, 0.f}, Cj[4] = {0.f, 0.f, 0.f, 0.f};
     bool far = false;
     if (split) {
-      if (jg >= n) {
-        far = true;  // sentinel-only group: every term is an exact zero on either path
+      if (jg >= n || ib[0] > ib[3]) {
+        far = true;  // sentinel-only receivers or sources: every term is an exact zero on either path
       } else {
         const float* gb = a.gbox + (int64_t)(B.gbase + jg / 64) * 6;
         float gap2 = 0.f;
