@@ -137,9 +137,10 @@ typedef struct {
                             Sec. 3 for every pair; f in 1..4 orders each bunch
                             along a Morton curve every evaluation and uses plain
                             FP32 separations for a 64-source group whose box is
-                            farther than D = U 2^-f from the box of a
-                            wavefront's receivers (U: largest scaled coordinate
-                            of the bunch).
+                            farther than D = 2^-f min(U, (|a| + |b|)/2) from
+                            the box of a wavefront's receivers (U: largest
+                            scaled coordinate of the bunch; a, b: per-axis
+                            largest |scaled coordinate| of the two boxes).
                             Each such term then differs from the hi/lo term by
                             at most 2 sqrt(3) 2^-23 2^f relative (6.6e-6 at
                             f = 4, inside the mixed tolerance).                 */

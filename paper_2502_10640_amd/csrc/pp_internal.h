@@ -109,10 +109,11 @@ struct SymArgs {
   int32_t r0;
   int32_t nbt;             // blocks over all bunches
   // near/far split (needs the spatial sort): a source group whose box is
-  // farther than near_frac * U from a wavefront's receiver box uses plain FP32
+  // farther than near_frac * min(U, (|a| + |b|) / 2) from a wavefront's receiver
+  // box (a, b: the boxes' per-axis largest |coordinate|) uses plain FP32
   // separations; near_frac = 0 keeps hi/lo separations everywhere
   float near_frac;
-  const float* gbox;       // [group][6]: min xyz, max xyz of the FP32 high parts
+  const float* gbox;       // [group][GBOX]: min xyz, max xyz of the FP32 high parts, |b|
   const uint32_t* ubits;   // per-bunch bound U on |scaled coordinate| (float bits)
 };
 
@@ -131,6 +132,9 @@ struct SymFoldArgs {
 
 // Spatial sort (pp_sort.hip): keys per tile of the radix sort.
 constexpr int SORT_TILE = 2048;
+// Group box record: min xyz, max xyz, then |b| = the norm of the per-axis
+// largest |coordinate| over the box, then padding.
+constexpr int GBOX = 8;
 
 struct SortArgs {
   const BunchDev* bunches;

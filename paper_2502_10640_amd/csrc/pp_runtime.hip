@@ -84,7 +84,7 @@ struct pp_ctx {
   uint32_t* hist = nullptr;        // 256 x (sort tiles + 1): histograms, then digit totals
   int32_t* rank = nullptr;         // sorted slot of each particle
   uint32_t* ubits = nullptr;       // per-bunch coordinate bound
-  float* gbox = nullptr;           // 6 x 64-particle groups
+  float* gbox = nullptr;           // GBOX x 64-particle groups
   int64_t n_in = 0;                // particles inside bunches
   int32_t n_groups = 0, n_blocks = 0;
   void* hpin = nullptr;        // pinned host staging for every host<->device copy
@@ -256,7 +256,7 @@ pp_status build_sym(pp_ctx* c) {
     PP_HIP(c, dalloc(&c->hist, 256 * (tiles + 1)));  // + 256 digit totals
     PP_HIP(c, dalloc(&c->rank, n));
     PP_HIP(c, dalloc(&c->ubits, (size_t)c->nb));
-    PP_HIP(c, dalloc(&c->gbox, 6 * (size_t)c->n_groups));
+    PP_HIP(c, dalloc(&c->gbox, (size_t)ppk::GBOX * (size_t)c->n_groups));
   }
   return h2d(c, c->sitems, items.data(), items.size() * sizeof(ppk::SymItem));
 }

@@ -5,9 +5,11 @@
 // their (scaled, FP32 high part) positions, so that a block of consecutive
 // particles is compact in space.  Source groups of 64 whose bounding box lies
 // farther than D from a wavefront's receiver box can then use plain FP32
-// separations (hi_i - hi_j): the rounding of the positions to FP32 changes a
-// pair term by at most 2 sqrt(3) 2^-23 U / D relative (U bounds every scaled
-// coordinate of the bunch), while closer groups keep the hi/lo separations.
+// separations (hi_i - hi_j): the rounding of the positions to FP32 moves a
+// separation by at most 2^-24 (|a| + |b|) (a, b: the two boxes' per-axis
+// largest |coordinate|, both below U, the bunch's bound), so a pair term
+// changes by at most 2^-23 (|a| + |b|) / D relative, while closer groups keep
+// the hi/lo separations.  This file computes U, the order and the group boxes.
 //
 // The sort is a stable least-significant-digit radix sort with 8-bit digits:
 // tile histograms (order-free LDS counts), a digit-major exclusive scan, and a
@@ -261,8 +263,15 @@ __global__ __launch_bounds__(256) void gbox_kernel(SortArgs a, int32_t n_groups_
       hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], d));
     }
   }
-  const float v = l == 0 ? lo[0] : l == 1 ? lo[1] : l == 2 ? lo[2] : l == 3 ? hi[0] : l == 4 ? hi[1] : hi[2];
-  if (l < 6) a.gbox[(int64_t)g * 6 + l] = v;
+  float s2 = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float m = fmaxf(fabsf(lo[c]), fabsf(hi[c]));
+    s2 = fmaf(m, m, s2);
+  }
+  const float v = l == 0 ? lo[0] : l == 1 ? lo[1] : l == 2 ? lo[2] : l == 3 ? hi[0] : l == 4 ? hi[1]
+                : l == 5 ? hi[2] : l == 6 ? sqrtf(s2) : 0.f;
+  if (l < GBOX) a.gbox[(int64_t)g * GBOX + l] = v;
 }
 
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }

@@ -160,13 +160,13 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
   // choice is uniform over the wavefront and may differ between wavefronts
   const bool split = !DIAG && a.near_frac > 0.f;
   float ib[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  float dfar2 = 0.f;
+  float ubound = 0.f, anorm = 0.f;
   if (split) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int gl = ibase / 64 + w * K + k;  // group of the bunch
       if (gl * 64 < n) {
-        const float* gx = a.gbox + (int64_t)(B.gbase + gl) * 6;
+        const float* gx = a.gbox + (int64_t)(B.gbase + gl) * GBOX;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           ib[c] = fminf(ib[c], gx[c]);
@@ -174,8 +174,19 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
         }
       }
     }
-    const float dfar = a.near_frac * __uint_as_float(a.ubits[it.b]);
-    dfar2 = dfar * dfar;
+    // dropping lo moves separation component c by at most 2^-24 (|u_i,c| + |u_j,c|):
+    // the threshold scales with the coordinate sizes of the two boxes, capped by
+    // the bunch bound U
+    ubound = __uint_as_float(a.ubits[it.b]);
+    if (ib[0] <= ib[3]) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float m = fmaxf(fabsf(ib[c]), fabsf(ib[3 + c]));
+        s2 = fmaf(m, m, s2);
+      }
+      anorm = sqrtf(s2);
+    }
   }
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], qi[K];
@@ -228,14 +239,17 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
       if (jg >= n || ib[0] > ib[3]) {
         far = true;  // sentinel-only receivers or sources: every term is an exact zero on either path
       } else {
-        const float* gb = a.gbox + (int64_t)(B.gbase + jg / 64) * 6;
+        const float* gb = a.gbox + (int64_t)(B.gbase + jg / 64) * GBOX;
         float gap2 = 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const float d = fmaxf(0.f, fmaxf(gb[c] - ib[3 + c], ib[c] - gb[3 + c]));
           gap2 = fmaf(d, d, gap2);
         }
-        far = gap2 > dfar2;
+        // D = near_frac * min(U, (|a| + |b|) / 2), |a|, |b| the norms of the boxes'
+        // per-axis largest |coordinate| (|b| stored with the group box)
+        const float dfar = a.near_frac * fminf(ubound, 0.5f * (anorm + gb[6]));
+        far = gap2 > dfar * dfar;
       }
     }
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
