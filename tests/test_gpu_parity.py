@@ -565,3 +565,23 @@ def test_full_size_sampled_parity_sweep_64(orc):
         assert e[0] <= TOL["mixed"] and e[1] <= TOL["mixed"], (k, b.n, e)
         assert l2_rel(got["phi"], ref["phi"]) <= TOL["mixed"], k
     print(f"    sweep_64 worst over bunches: l2={worst[0]:.3e} cond_max={worst[1]:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("variant", ["ordered", "symmetric_far"])
+def test_graph_replays_match_eager_steps_one_by_one(variant):
+    """Several replays of one captured step graph, with eager work (field
+    evaluations, host copies, synchronisations) between them: after every
+    replay the state equals that of a twin context stepped without graphs."""
+    tun = {"graph_steps": 4}
+    if variant == "symmetric_far":
+        tun.update({"symmetric": 1, "i_per_lane": 1, "far_split": 3})
+    b = wl.workload("gaussian_65536", n_override=5000)[0]
+    say(f"graph replays one by one ({variant})")
+    with Sim([b], "mixed", tuning=tun) as g, Sim([b], "mixed", tuning=tun) as e:
+        for rep in range(4):
+            g.step_batched(4, graph=True)
+            e.push(4)
+            g.field(want_phi=True)  # eager work on the graph's context between replays
+            g.sync()
+            for k in ("x", "vx", "z", "vz"):
+                np.testing.assert_array_equal(g.host(k), e.host(k), err_msg=f"replay {rep} {k}")
