@@ -126,13 +126,15 @@ typedef struct {
                             interactions (16..30).  The split depends only on
                             the bunch's own size, so a bunch gives the same
                             bits alone or in a batch.                           */
-  int32_t grid_per_cu;   /* persistent workgroups per compute unit, 1..16       */
+  int32_t grid_per_cu;   /* ordered kernel: workgroups per compute unit of its
+                            persistent grid (work lists over 65536 items), and
+                            the items per CU a bunch is split into, 1..16      */
   int32_t graph_steps;   /* steps captured per hipGraph with PP_GRAPH, 1..1024   */
   int32_t symmetric;     /* PP_MIXED only: 1 evaluates each unordered pair once
                             (Newton's third law, Eq. (A) antisymmetry) in rounds
                             of block pairs, i_per_lane 1, 2 or 4 (blocks of
                             512 i_per_lane particles); 0 evaluates every ordered
-                            pair in the persistent kernel                       */
+                            pair in the ordered-pair kernel                     */
   int32_t far_split;     /* symmetric only: 0 keeps the hi/lo separations of
                             Sec. 3 for every pair; f in 1..4 orders each bunch
                             along a Morton curve every evaluation and uses plain
@@ -176,8 +178,8 @@ pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi)
 pp_status pp_push(pp_ctx *ctx, int64_t n_steps);
 
 /* Same trajectory as pp_push (bitwise, for the same tiling), driven by the
- * batched scheduler: one persistent pair-sum kernel per step serving every
- * bunch from one work list; with PP_GRAPH the steps are replayed from hipGraphs
+ * batched scheduler: one pair-sum stage per step serving every bunch from one
+ * work list (or one round schedule); with PP_GRAPH the steps are replayed from hipGraphs
  * captured on first use; with PP_AUTOTUNE the tiling is chosen by timing
  * candidates once (the choice is kept in the context); PP_CHECK as above.
  * Asynchronous unless PP_AUTOTUNE runs a search or PP_CHECK is given. */

@@ -1,8 +1,10 @@
 // pp_kernels.hip -- gfx950 kernels of the PP library.
 //
 // Hot path (arXiv 2502.10640 Sec. 2.1): the direct pair sum of Eq. (B) with
-// Plummer softening, one persistent kernel over a flattened work list that
-// serves every bunch of the context.  Receivers sit in registers (i_per_lane
+// Plummer softening over all ordered pairs, one kernel over a flattened work
+// list that serves every bunch of the context (one workgroup per item for
+// short lists, a persistent grid with a work counter for long ones; the
+// symmetric schedule for large bunches is in pp_sym.hip).  Receivers sit in registers (i_per_lane
 // per lane), sources are staged through LDS in tiles of JT particles loaded
 // with coalesced SoA reads and read back as same-address (broadcast) LDS loads.
 // The pairwise law is evaluated on the vector ALUs with v_rsq_f32 (mixed) or
@@ -12,7 +14,7 @@
 // Per-receiver sums are exact-order deterministic: a plain sum over sum_tile
 // sources, then a two-sum (Knuth) into a running (sum, compensation) pair.
 // Each work item writes its own partial slot; the final kernel adds the
-// chunk partials in chunk order in FP64.  No floating-point atomics anywhere;
+// chunk partials in a fixed order in FP64.  No floating-point atomics anywhere;
 // the only atomic is the work counter, which decides who computes an item,
 // never the order of an addition.
 #include "pp_device.h"

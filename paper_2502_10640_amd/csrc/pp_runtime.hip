@@ -1,9 +1,11 @@
 // pp_runtime.hip -- host runtime behind the C ABI of include/pp.h.
 //
 // Owns the context: argument validation, device scratch, the per-bunch
-// constants, the work list of the persistent pair-sum kernel, the step
-// sequence (drift+pack -> pair sum -> combine+kick), hipGraph replay of the
-// step loop, diagnostics, kernel timing and the tiling autotuner.
+// constants, the work list of the ordered-pair kernel and the round/band
+// schedule of the symmetric one, the step sequence (drift+pack -> pair sum ->
+// combine+kick, the kick fused with the next drift inside a run), hipGraph
+// replay of the step loop, diagnostics, kernel timing, the default tiling and
+// the autotuner.
 #include "pp.h"
 #include "pp_internal.h"
 
