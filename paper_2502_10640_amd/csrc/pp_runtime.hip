@@ -9,7 +9,10 @@
 #include "pp.h"
 #include "pp_internal.h"
 
+#include <sys/stat.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -704,14 +707,21 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
   return found;
 }
 
+// mkdir -p without a shell: create each missing prefix of dir (0755)
+bool make_dirs(const std::string& dir) {
+  for (size_t pos = 1; pos <= dir.size(); ++pos) {
+    if (pos == dir.size() || dir[pos] == '/') {
+      const std::string prefix = dir.substr(0, pos);
+      if (::mkdir(prefix.c_str(), 0755) != 0 && errno != EEXIST) return false;
+    }
+  }
+  return true;
+}
+
 void tune_store(const std::string& key, const pp_tuning& t) {
   const std::string path = tune_path();
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "'";
-    if (std::system(cmd.c_str()) != 0) return;
-  }
+  if (slash != std::string::npos && slash > 0 && !make_dirs(path.substr(0, slash))) return;
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "

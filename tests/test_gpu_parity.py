@@ -500,7 +500,7 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     without the far split), keeps the fastest one that reproduces the field,
     and stores it; a second context of the same shape reuses the stored one."""
     b = wl.workload("gaussian_65536", n_override=20000)[0]
-    cache = tmp_path / "tune.txt"
+    cache = tmp_path / "it's a" / "new dir" / "tune.txt"  # created without a shell, quotes and all
     monkeypatch.setenv("PP_TUNE_CACHE", str(cache))
     say(f"autotune mixed n={b.n}, cache {cache}")
     with Sim([b], "mixed") as sim:
