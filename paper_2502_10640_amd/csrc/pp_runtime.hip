@@ -696,12 +696,17 @@ std::string tune_path() {
 }
 
 bool tune_lookup(const std::string& key, pp_tuning* t) {
+  // one record per line: key and the 7 tuning fields; other lines are skipped
   std::ifstream f(tune_path());
-  std::string k;
-  pp_tuning v{};
+  std::string line;
   bool found = false;
-  while (f >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
-         v.symmetric >> v.far_split) {
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k, extra;
+    pp_tuning v{};
+    if (!(in >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
+          v.symmetric >> v.far_split) || (in >> extra))
+      continue;
     if (k == key) { *t = v; found = true; }
   }
   return found;

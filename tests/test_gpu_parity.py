@@ -502,8 +502,11 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     b = wl.workload("gaussian_65536", n_override=20000)[0]
     cache = tmp_path / "it's a" / "new dir" / "tune.txt"  # created without a shell, quotes and all
     monkeypatch.setenv("PP_TUNE_CACHE", str(cache))
+    junk = "not a record\ngfx950:old:format 1 64 22 4 16 0\n"  # skipped, and must not shift later records
     say(f"autotune mixed n={b.n}, cache {cache}")
     with Sim([b], "mixed") as sim:
+        cache.parent.mkdir(parents=True)
+        cache.write_text(junk)
         sim.step_batched(2, graph=False, autotune=True)
         tuned = sim.tuning()
         got = gpu_field(sim)
@@ -511,7 +514,9 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     print(f"    tuning chosen: {tuned}", flush=True)
     ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
     check_field(got, ref, TOL["mixed"], "autotuned tiling")
-    line = cache.read_text().split()
+    lines = cache.read_text().splitlines()
+    assert lines[:2] == junk.splitlines() and len(lines) == 3
+    line = lines[2].split()
     assert len(line) == 8 and line[0].startswith("gfx950:")
     assert [int(v) for v in line[1:]] == [tuned[k] for k in ("i_per_lane", "sum_tile", "chunk_pairs_log2",
                                                                "grid_per_cu", "graph_steps", "symmetric",
@@ -519,7 +524,7 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     with Sim([b], "mixed") as sim:
         sim.step_batched(1, graph=False, autotune=True)
         assert sim.tuning() == tuned
-    assert len(cache.read_text().splitlines()) == 1  # found in the cache: no second search
+    assert len(cache.read_text().splitlines()) == 3  # found in the cache: no second search
 
 
 # ---------------------------------------------------------------------------
