@@ -33,34 +33,51 @@ class Simulation:
             arrays, offsets = _with_gaps(arrays, offsets, gap)
         self.offsets = offsets
         self.n_total = int(arrays[0].shape[0])
-        self.t = {name: torch.from_numpy(np.ascontiguousarray(a)).to(self.device) for name, a in zip(FIELDS, arrays)}
         prec = pp.PP_MIXED if precision == "mixed" else pp.PP_FP64
         desc = [(off, n, b.weight, b.softening, b.dt) for (off, n), b in zip(offsets, self.bunches)]
+        # the context lives on this device and enqueues on this stream; every call
+        # below runs with both current, so torch's own work (copies, zero fills)
+        # is ordered with the library's
         self.stream = torch.cuda.current_stream(self.device)
-        self.ctx = pp.pp_create(desc, self.n_total, [self.t[k].data_ptr() for k in FIELDS], prec,
-                                self.stream.cuda_stream)
-        if tuning:
-            pp.pp_set_tuning(self.ctx, **tuning)
+        with self._on():
+            self.t = {name: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+                      for name, a in zip(FIELDS, arrays)}
+            self.ctx = pp.pp_create(desc, self.n_total, [self.t[k].data_ptr() for k in FIELDS], prec,
+                                    self.stream.cuda_stream)
+            if tuning:
+                pp.pp_set_tuning(self.ctx, **tuning)
+
+    def _on(self):
+        """Make this simulation's device and stream current (a context manager)."""
+        import contextlib
+        stack = contextlib.ExitStack()
+        stack.enter_context(self.torch.cuda.device(self.device))
+        stack.enter_context(self.torch.cuda.stream(self.stream))
+        return stack
 
     # -- the C entry points ------------------------------------------------
     def field(self, want_phi: bool = False):
         torch = self.torch
-        out = {k: torch.zeros(self.n_total, dtype=torch.float64, device=self.device) for k in ("ex", "ey", "ez")}
-        if want_phi:
-            out["phi"] = torch.zeros(self.n_total, dtype=torch.float64, device=self.device)
-        pp.pp_field(self.ctx, out["ex"].data_ptr(), out["ey"].data_ptr(), out["ez"].data_ptr(),
-                    out["phi"].data_ptr() if want_phi else None)
+        with self._on():
+            out = {k: torch.zeros(self.n_total, dtype=torch.float64, device=self.device) for k in ("ex", "ey", "ez")}
+            if want_phi:
+                out["phi"] = torch.zeros(self.n_total, dtype=torch.float64, device=self.device)
+            pp.pp_field(self.ctx, out["ex"].data_ptr(), out["ey"].data_ptr(), out["ez"].data_ptr(),
+                        out["phi"].data_ptr() if want_phi else None)
         return out
 
     def push(self, n_steps: int) -> None:
-        pp.pp_push(self.ctx, n_steps)
+        with self._on():
+            pp.pp_push(self.ctx, n_steps)
 
     def step_batched(self, n_steps: int, graph: bool = True, autotune: bool = False, check: bool = False) -> None:
         flags = (pp.PP_GRAPH if graph else 0) | (pp.PP_AUTOTUNE if autotune else 0) | (pp.PP_CHECK if check else 0)
-        pp.pp_step_batched(self.ctx, n_steps, flags)
+        with self._on():
+            pp.pp_step_batched(self.ctx, n_steps, flags)
 
     def diagnostics(self) -> List[dict]:
-        return pp.pp_diagnostics(self.ctx, len(self.bunches))
+        with self._on():
+            return pp.pp_diagnostics(self.ctx, len(self.bunches))
 
     def invalidate(self) -> None:
         pp.pp_invalidate(self.ctx)
@@ -69,15 +86,18 @@ class Simulation:
         return pp.pp_get_tuning(self.ctx)
 
     def set_tuning(self, **kw) -> None:
-        pp.pp_set_tuning(self.ctx, **kw)
+        with self._on():
+            pp.pp_set_tuning(self.ctx, **kw)
 
     def sync(self) -> None:
-        pp.pp_sync(self.ctx)
+        with self._on():
+            pp.pp_sync(self.ctx)
 
     # -- host views ---------------------------------------------------------
     def host(self, name: str) -> np.ndarray:
         self.sync()
-        return self.t[name].cpu().numpy()
+        with self._on():
+            return self.t[name].cpu().numpy()
 
     def bunch_slice(self, b: int) -> slice:
         off, n = self.offsets[b]
@@ -85,7 +105,8 @@ class Simulation:
 
     def close(self) -> None:
         if getattr(self, "ctx", None):
-            pp.pp_destroy(self.ctx)
+            with self._on():
+                pp.pp_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

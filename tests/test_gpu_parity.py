@@ -590,3 +590,20 @@ def test_graph_replays_match_eager_steps_one_by_one(variant):
             g.sync()
             for k in ("x", "vx", "z", "vz"):
                 np.testing.assert_array_equal(g.host(k), e.host(k), err_msg=f"replay {rep} {k}")
+
+
+def test_simulation_calls_under_another_current_stream(orc, gpu):
+    """The wrapper runs every call on its context's stream: a caller whose
+    current torch stream is another one still gets the right field (the output
+    tensors are zero-filled on the context's stream, ahead of the kernels)."""
+    torch = gpu
+    b = wl.workload("cold_sphere_2048")[0]
+    say("field with another torch stream current")
+    with Sim([b], "mixed") as sim:
+        other = torch.cuda.Stream()
+        with torch.cuda.stream(other):
+            f = sim.field(want_phi=True)
+            sim.push(2)
+            sim.sync()
+            got = {k: v.cpu().numpy() for k, v in f.items()}
+    check_field(got, oracle_field(orc, b), TOL["mixed"], "under another stream")
