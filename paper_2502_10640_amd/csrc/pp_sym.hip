@@ -37,11 +37,12 @@ namespace {
 // zeros in both directions.
 constexpr float SENTINEL = 1.5e19f;
 
-// steps of a source group unrolled per loop iteration (divides 16)
-#ifndef SYM_UNROLL
-#define SYM_UNROLL 16
-#endif
-static_assert(16 % SYM_UNROLL == 0, "the hand-off period is a whole number of iterations");
+// Steps of a source group unrolled per loop iteration (a divisor of the
+// 16-step hand-off period).  Measured on gfx950: 16 is fastest for 2 and 4
+// receivers per lane; with 1 per lane a 16-step body needs 129 VGPRs and 4
+// steps (75 VGPRs) is 14-24% faster.
+template <int K>
+constexpr int sweep_unroll() { return K == 1 ? 4 : 16; }
 
 __device__ __forceinline__ float lane_read(float v, int src_lane) {
   // value of v in lane src_lane of this wavefront (ds_bpermute: LDS crossbar, no LDS memory)
@@ -59,12 +60,14 @@ __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, cons
   // group is stored twice in LDS (entries 64..127 repeat 0..63), so step s
   // reads entry l + s with no wrap, at an immediate offset from the base of
   // its block of 16 steps.
+  constexpr int UNR = sweep_unroll<K>();
+  static_assert(16 % UNR == 0, "the hand-off period is a whole number of iterations");
   float aj[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int s0 = 0; s0 < 64; s0 += SYM_UNROLL) {
+  for (int s0 = 0; s0 < 64; s0 += UNR) {
     const float4* hb = sjh + (l + s0);
     const float4* lb = sjl + (l + s0);
 #pragma unroll
-    for (int u = 0; u < SYM_UNROLL; ++u) {
+    for (int u = 0; u < UNR; ++u) {
       const int s = s0 + u;
       const float4 h = hb[u];
       float dx[K], dy[K], dz[K], r2[K], inv[K];
