@@ -12,7 +12,8 @@ Prints one JSON line:
   roofline   the pair-sum kernel's achieved FP32 rate (20 flops per pair, the
              usual count for a softened inverse-square interaction) over its
              average duration, measured with HIP events on the stream it runs
-             on, against the 157.3 TFLOP/s FP32 vector peak of the MI355X
+             on, against the 157.3 TFLOP/s FP32 vector peak of the MI355X (the
+             FP64 path: its FP64 rate against the 78.6 TFLOP/s FP64 peak)
   cpu_baseline  the CPU oracle on a bounded sample of the same field evaluation
 """
 from __future__ import annotations
@@ -28,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 20
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "pair_sym_cold_sphere_1m_counters.json")
 
 
@@ -293,8 +295,12 @@ def main():
     print(f"[bench] {a.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     used_tuning = sim.tuning()
-    sym = a.precision == "mixed" and used_tuning.get("symmetric", 0) == 1
-    kernel = "pair_sym_kernel" if sym else f"pair_{a.precision}_kernel"
+    sym = used_tuning.get("symmetric", 0) == 1
+    if sym:
+        kernel = "pair_sym_kernel" if a.precision == "mixed" else "pair_sym64_kernel"
+    else:
+        kernel = f"pair_{a.precision}_kernel"
+    peak = PEAK_FP32_TFLOPS if a.precision == "mixed" else PEAK_FP64_TFLOPS
     roofline = None
     if prof["launches"] > 0 and prof["evaluations"] > 0:
         # pair-kernel time per field evaluation: the sum of its dispatches (one
@@ -302,8 +308,8 @@ def main():
         # schedule), timed with HIP events on the stream they run on
         eval_s = prof["total_ms"] / prof["evaluations"] * 1e-3
         achieved = FLOPS_PER_PAIR * pairs / eval_s / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+        roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None,
                     "kernel": kernel, "kernel_ms_per_evaluation": eval_s * 1e3,
                     "launches_per_evaluation": prof["launches"] / prof["evaluations"],
                     "avg_launch_ms": prof["total_ms"] / prof["launches"],

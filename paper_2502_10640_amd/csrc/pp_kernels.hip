@@ -4,12 +4,12 @@
 // Plummer softening over all ordered pairs, one kernel over a flattened work
 // list that serves every bunch of the context (one workgroup per item for
 // short lists, a persistent grid with a work counter for long ones; the
-// symmetric schedule for large bunches is in pp_sym.hip).  Receivers sit in registers (i_per_lane
-// per lane), sources are staged through LDS in tiles of JT particles loaded
-// with coalesced SoA reads and read back as same-address (broadcast) LDS loads.
-// The pairwise law is evaluated on the vector ALUs with v_rsq_f32 (mixed) or
-// v_rsq_f64 refined by two Newton steps (FP64); no MFMA: an inverse-cube law
-// is not a dense contraction.
+// symmetric schedules for large bunches are in pp_sym.hip and pp_sym64.hip).
+// Receivers sit in registers (i_per_lane per lane), sources are staged through
+// LDS in tiles of JT particles loaded with coalesced SoA reads and read back as
+// same-address (broadcast) LDS loads.  The pairwise law is evaluated on the
+// vector ALUs with v_rsq_f32 (mixed) or v_rsq_f64 and a series correction
+// (FP64, inv_r3_64); no MFMA: an inverse-cube law is not a dense contraction.
 //
 // Per-receiver sums are exact-order deterministic: a plain sum over sum_tile
 // sources, then a two-sum (Knuth) into a running (sum, compensation) pair.
@@ -18,6 +18,7 @@
 // the only atomic is the work counter, which decides who computes an item,
 // never the order of an addition.
 #include "pp_device.h"
+#include "pp_device64.h"
 #include "pp_internal.h"
 
 #include <cfloat>
@@ -172,18 +173,6 @@ void pair_mixed_kernel(PairArgs a, int32_t sum_tile) {
 // ---------------------------------------------------------------------------
 // FP64 pair sum (the plain reference path on the GPU).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double rsq64(double r2) {
-  // v_rsq_f64 then two Newton steps y <- y (1 + (1 - r2 y^2) / 2)
-  double y = __builtin_amdgcn_rsq(r2);
-  double h = r2 * y;
-  double e = fma(-h, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  h = r2 * y;
-  e = fma(-h, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  return y;
-}
-
 template <int K, bool UQ, bool PHI, bool DIAG>
 __device__ __forceinline__ void acc_fp64(const double4* __restrict__ sj, int jb, int je, int jbase,
                                          const int (&li)[K], const double (&xi)[K], const double (&yi)[K],
@@ -203,9 +192,9 @@ __device__ __forceinline__ void acc_fp64(const double4* __restrict__ sj, int jb,
         self = (jbase + jj == li[k]);
         if (self) r2 = 1.0;
       }
-      const double inv = rsq64(r2);
-      const double inv2 = inv * inv;
-      double s = UQ ? inv2 * inv : (p.w * inv) * inv2;
+      double inv = 0.0;
+      const double s3 = inv_r3_64<PHI>(r2, inv);
+      double s = UQ ? s3 : p.w * s3;
       double ph = UQ ? inv : p.w * inv;
       if (DIAG) {
         if (self) { s = 0.0; ph = 0.0; }
@@ -371,6 +360,15 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   const int64_t li = i - B.off;
   const bool want_phi = (MODE == FIN_FIELD) && a.phi != nullptr;
   double ex = 0.0, ey = 0.0, ez = 0.0, ph = 0.0;
+  if (!MIXED && a.sym) {
+    // FP64 symmetric accumulators: receiver side (S, C) then source side (S, C)
+    const double* f = a.pd;
+    const int64_t P = a.P;
+    ex = (f[0 * P + i] + f[3 * P + i]) + (f[6 * P + i] + f[9 * P + i]);
+    ey = (f[1 * P + i] + f[4 * P + i]) + (f[7 * P + i] + f[10 * P + i]);
+    ez = (f[2 * P + i] + f[5 * P + i]) + (f[8 * P + i] + f[11 * P + i]);
+    if (want_phi) ph = (f[12 * P + i] + f[13 * P + i]) + (f[14 * P + i] + f[15 * P + i]);
+  }
   if (MIXED && a.sym) {
     // receiver side (S, C) then source side (S, C), in that order
     const float* f = a.pf;
@@ -383,7 +381,7 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   }
   // this lane's chunks in chunk order
 #pragma unroll 4
-  for (int c = t; c < ((MIXED && a.sym) ? 0 : B.n_chunks); c += L) {
+  for (int c = t; c < (a.sym ? 0 : B.n_chunks); c += L) {
     const int64_t s = B.pbase + (int64_t)c * B.n + li;
     if (MIXED) {
       ex += (double)a.pf[0 * a.P + s] + (double)a.pf[3 * a.P + s];
@@ -726,7 +724,7 @@ hipError_t go_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t 
 }
 
 hipError_t launch_final(const FinalArgs& a, bool mixed, FinalMode mode, hipStream_t s) {
-  if (mixed && a.sym) return go_final<1>(a, mixed, mode, s);
+  if (a.sym) return go_final<1>(a, mixed, mode, s);
   return go_final<FIN_LANES>(a, mixed, mode, s);
 }
 

@@ -8,6 +8,7 @@
 // the autotuner.
 #include "pp.h"
 #include "pp_internal.h"
+#include "pp_sym64.h"
 
 #include <sys/stat.h>
 
@@ -79,8 +80,8 @@ struct pp_ctx {
   size_t sitems_cap = 0;
   struct Band { int32_t first, count, r0, r1; };
   std::vector<Band> bands;         // one item launch + one fold per band of rounds
-  float* acc = nullptr;            // symmetric accumulators, SYM_PLANES x n_total
-  float* slot = nullptr;           // per-item partial slots of one band
+  void* acc = nullptr;             // symmetric accumulators, SYM_PLANES x n_total (FP32 or FP64)
+  void* slot = nullptr;            // per-item partial slots of one band (FP32 or FP64)
   size_t slot_bytes = 0;
   // spatial sort of the near/far split (allocated on first use)
   float* smir = nullptr;           // 7 planes in sorted order
@@ -112,9 +113,12 @@ struct pp_ctx {
   float* xh() const { return mir; }
   float* plane(int k) const { return mir + (size_t)k * (size_t)n_total; }
   bool mixed() const { return prec == PP_MIXED; }
-  bool sym() const { return prec == PP_MIXED && tun.symmetric != 0; }
-  bool far() const { return sym() && tun.far_split > 0; }
+  bool sym() const { return tun.symmetric != 0; }
+  bool far() const { return mixed() && sym() && tun.far_split > 0; }
+  size_t acc_elem() const { return mixed() ? sizeof(float) : sizeof(double); }
   int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
+  // particles per block of the symmetric schedule
+  int64_t sym_block() const { return (int64_t)(mixed() ? ppk::SYM_WG : ppk::SYM64_WG) * tun.i_per_lane; }
 };
 
 namespace {
@@ -188,7 +192,7 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric schedule.  Blocks of SYM_WG * i_per_lane particles per bunch; round
+// Symmetric schedule.  Blocks of sym_block() particles per bunch; round
 // 0 holds every diagonal item, round d >= 1 the block pairs (I, I + d mod nb)
 // (for even nb and d = nb/2 only I < nb/2), so each unordered block pair occurs
 // exactly once and a round gives every block at most one partial per side.
@@ -198,7 +202,7 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 constexpr size_t kSlotBytes = size_t(8) << 30;
 
 pp_status build_sym(pp_ctx* c) {
-  const int64_t BS = (int64_t)ppk::SYM_WG * c->tun.i_per_lane;
+  const int64_t BS = c->sym_block();
   std::vector<ppk::SymItem> items;
   std::vector<int64_t> round_first;
   int64_t maxr = 0;
@@ -223,7 +227,7 @@ pp_status build_sym(pp_ctx* c) {
   round_first.push_back((int64_t)items.size());
   if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
   const int64_t rounds = maxr + 1;
-  const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * sizeof(float);
+  const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * c->acc_elem();
   // the fewest bands that fit, of equal size (no short last band leaving the GPU half idle)
   const int64_t band_max = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
   const int64_t n_bands = (rounds + band_max - 1) / band_max;
@@ -249,7 +253,7 @@ pp_status build_sym(pp_ctx* c) {
     PP_HIP(c, dalloc(&c->sitems, items.size()));
     c->sitems_cap = items.size();
   }
-  if (!c->acc) PP_HIP(c, dalloc(&c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total));
+  if (!c->acc) PP_HIP(c, hipMalloc(&c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total * c->acc_elem()));
   if (c->far() && !c->smir) {
     // host-side shape checks of what the sort kernels assume
     if (c->n_total > INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "far split: more than 2^31 - 1 particles");
@@ -304,7 +308,7 @@ pp_status build_items(pp_ctx* c) {
     B.pbase = pbase;
     pbase += nch * n;
     // spatial-sort bases: compacted keys, 64-particle groups, symmetric blocks
-    const int64_t bs = (int64_t)ppk::SYM_WG * c->tun.i_per_lane;
+    const int64_t bs = c->sym_block();
     if (cbase + n > INT32_MAX || gbase + (n + 63) / 64 > INT32_MAX)
       return set_err(c, PP_ERR_INVALID_ARG, "work list: more than 2^31 - 1 particles in bunches");
     B.cstart = cbase;
@@ -408,8 +412,8 @@ ppk::FinalArgs final_args(pp_ctx* c) {
   a.bunches = c->dbunch;
   a.bid = c->bid;
   a.n_total = c->n_total;
-  a.pf = c->sym() ? c->acc : (const float*)c->part;
-  a.pd = (const double*)c->part;
+  a.pf = (c->sym() && c->mixed()) ? (const float*)c->acc : (const float*)c->part;
+  a.pd = (c->sym() && !c->mixed()) ? (const double*)c->acc : (const double*)c->part;
   a.P = c->sym() ? c->n_total : c->P;
   a.sym = c->sym() ? 1 : 0;
   a.rank = c->far() ? c->rank : nullptr;
@@ -463,14 +467,39 @@ pp_status mark(pp_ctx* c, bool timed, bool begin, hipStream_t s) {
 pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
   pp_status st;
   if (timed) ++c->prof_evals;
-  if (c->sym()) {
+  if (c->sym() && !c->mixed()) {
+    ppk::SymArgs64 sa{};
+    sa.bunches = c->dbunch;
+    sa.items = c->sitems;
+    sa.x = c->st.x; sa.y = c->st.y; sa.z = c->st.z;
+    sa.qt = c->qt64;
+    sa.slot = (double*)c->slot;
+    sa.nbt = c->n_blocks;
+    ppk::SymFoldArgs64 fa{};
+    fa.bunches = c->dbunch;
+    fa.bid = c->bid;
+    fa.n_total = c->n_total;
+    fa.slot = (const double*)c->slot;
+    fa.acc = (double*)c->acc;
+    fa.nbt = c->n_blocks;
+    fa.block_size = (int32_t)c->sym_block();
+    for (const auto& B : c->bands) {
+      sa.r0 = B.r0;
+      if ((st = mark(c, timed, true, s)) != PP_OK) return st;
+      PP_HIP(c, ppk::launch_sym64(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
+      if ((st = mark(c, timed, false, s)) != PP_OK) return st;
+      fa.r0 = B.r0;
+      fa.r1 = B.r1;
+      PP_HIP(c, ppk::launch_sym64_fold(fa, phi, s));
+    }
+  } else if (c->sym()) {
     ppk::SymArgs sa{};
     sa.bunches = c->dbunch;
     sa.items = c->sitems;
     sa.xh = c->plane(0); sa.yh = c->plane(1); sa.zh = c->plane(2);
     sa.xl = c->plane(3); sa.yl = c->plane(4); sa.zl = c->plane(5);
     sa.qt = c->plane(6);
-    sa.slot = c->slot;
+    sa.slot = (float*)c->slot;
     sa.nbt = c->n_blocks;
     if (c->far()) {
       ppk::SortArgs so{};
@@ -511,10 +540,10 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
     fa.bunches = c->dbunch;
     fa.bid = c->bid;
     fa.n_total = c->n_total;
-    fa.slot = c->slot;
-    fa.acc = c->acc;
+    fa.slot = (const float*)c->slot;
+    fa.acc = (float*)c->acc;
     fa.nbt = c->n_blocks;
-    fa.block_size = ppk::SYM_WG * c->tun.i_per_lane;
+    fa.block_size = (int32_t)c->sym_block();
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
@@ -612,20 +641,25 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.grid_per_cu < 1 || t.grid_per_cu > 16) return false;
   if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
   if (t.symmetric != 0 && t.symmetric != 1) return false;
-  if (t.symmetric && (!mixed || k == 8)) return false;
+  // symmetric: 1, 2 or 4 receivers per lane (FP64: 1 or 2); the near/far split is mixed only
+  if (t.symmetric && (k == 8 || (!mixed && k > 2))) return false;
   // far_split <= 4 keeps the per-term bound 2 sqrt(3) 2^-23 2^f at 6.6e-6, inside the mixed tolerance
-  if (t.far_split < 0 || t.far_split > 4 || (t.far_split > 0 && !t.symmetric)) return false;
+  if (t.far_split < 0 || t.far_split > 4 || (t.far_split > 0 && (!t.symmetric || !mixed))) return false;
   return true;
 }
 
-// Default tiling from the bunch sizes.  The symmetric schedule (with the
-// near/far split at D = U / 8) is taken when a cost model says it is cheaper
-// than the ordered-pair kernel.  Costs in units of one ordered pair in the
-// ordered kernel, from measurements on MI355X: an off-diagonal unordered pair
-// 1.02, a diagonal-block pair 0.6, times 1.1 for 2 receivers per lane instead
-// of 4 (1 per lane measured ~2x slower and is left to the autotuner); padded
-// blocks are paid in full, and the cost is divided by the fill of the last
-// wave of workgroups (items over resident slots times the waves they need).
+// Default tiling from the bunch sizes.  The symmetric schedule (mixed: with
+// the near/far split at D = U / 8) is taken when a cost model says it is
+// cheaper than the ordered-pair kernel.  Costs in units of one ordered pair in
+// the ordered kernel of the same precision, from measurements on MI355X: an
+// off-diagonal unordered pair 1.02, a diagonal-block pair 0.6, times a
+// per-variant factor (mixed: 1.0 at 4 receivers per lane, 1.1 at 2; FP64: 1.55
+// at 2, the FP64 sweep gaining less over its ordered kernel because the
+// source-side rotation is two ds_bpermute per double and the fold of FP64
+// slots costs ~4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
+// is left to the autotuner.  Padded blocks are paid in full, and the cost is
+// divided by the fill of the last wave of workgroups (items over resident
+// slots times the waves they need).
 pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   int64_t min_n = INT64_MAX;
   double ordered = 0.0;
@@ -640,25 +674,30 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   t.grid_per_cu = 4;
   t.graph_steps = 16;
   t.symmetric = 0;
-  if (!mixed) return t;
+  struct Variant { int k; double bs, eff; int blocks_per_cu; };
+  std::vector<Variant> vars;
+  if (mixed) {
+    vars.push_back({4, (double)ppk::SYM_WG * 4, 1.0, ppk::sym_blocks_per_cu(4)});
+    vars.push_back({2, (double)ppk::SYM_WG * 2, 1.1, ppk::sym_blocks_per_cu(2)});
+  } else {
+    vars.push_back({2, (double)ppk::SYM64_WG * 2, 1.55, ppk::sym64_blocks_per_cu(2)});
+  }
   double best = ordered;
-  for (int k : {4, 2}) {
-    const double bs = (double)ppk::SYM_WG * k;
-    const double eff = k == 4 ? 1.0 : 1.1;
+  for (const Variant& v : vars) {
     double cost = 0.0, items = 0.0;
     for (const auto& b : hb) {
-      const double nbk = std::ceil((double)b.n / bs);
-      cost += bs * bs * (0.6 * nbk + 1.02 * nbk * (nbk - 1.0) / 2.0) * eff;
+      const double nbk = std::ceil((double)b.n / v.bs);
+      cost += v.bs * v.bs * (0.6 * nbk + 1.02 * nbk * (nbk - 1.0) / 2.0) * v.eff;
       items += nbk * (nbk + 1.0) / 2.0;
     }
-    const double slots = (double)cus * ppk::sym_blocks_per_cu(k);
+    const double slots = (double)cus * v.blocks_per_cu;
     const double fill = items / (slots * std::ceil(items / slots));
     cost /= fill;
     if (cost < best) {
       best = cost;
       t.symmetric = 1;
-      t.i_per_lane = k;
-      t.far_split = 3;  // per-term change at most 3.3e-6 relative
+      t.i_per_lane = v.k;
+      t.far_split = mixed ? 3 : 0;  // mixed: per-term change at most 3.3e-6 relative
     }
   }
   return t;
@@ -671,7 +710,8 @@ pp_status apply_tuning(pp_ctx* c, const pp_tuning& t) {
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: coordinate search over (i_per_lane, sum_tile, grid_per_cu) by
+// Autotuner: coordinate search over (i_per_lane, sum_tile, grid_per_cu,
+// chunk size, schedule, far split) by
 // timed field evaluations on the context's own bunches; a candidate must
 // reproduce the field of the starting tiling (relative L2 within the
 // precision's tolerance) to be kept.  Choices are cached in a text file
@@ -682,7 +722,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v3";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v4";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -818,7 +858,7 @@ pp_status autotune(pp_ctx* c) {
   const int gpc[] = {1, 2, 4, 8};
   for (int g : gpc) { pp_tuning t = best; t.grid_per_cu = g; if ((s = trial(t)) != PP_OK) return s; }
   for (int cp : {18, 20, 22, 24}) { pp_tuning t = best; t.chunk_pairs_log2 = cp; if ((s = trial(t)) != PP_OK) return s; }
-  if (c->mixed()) {
+  {
     for (int sym : {0, 1}) {
       for (int k : {1, 2, 4}) {
         pp_tuning t = best;

@@ -1,0 +1,45 @@
+// pp_sym64.h -- the FP64 symmetric pair sum (pp_sym64.hip): arguments and
+// launchers (not part of the C ABI).
+#pragma once
+
+#include "pp_internal.h"
+
+namespace ppk {
+
+// Same rounds, bands and slot indexing as the mixed symmetric schedule
+// (SymArgs), with FP64 sources (unscaled SI positions, normalised charges)
+// and FP64 partial slots.
+struct SymArgs64 {
+  const BunchDev* bunches;
+  const SymItem* items;
+  const double *x, *y, *z, *qt;
+  double* slot;            // (((r - r0) * nbt + block) * 2 + side) * SLOT_PLANES + plane) * block_size + offset
+  int32_t r0;
+  int32_t nbt;
+};
+
+struct SymFoldArgs64 {
+  const BunchDev* bunches;
+  const int32_t* bid;
+  int64_t n_total;
+  const double* slot;
+  double* acc;             // SYM_PLANES planes of length n_total
+  int32_t r0, r1;
+  int32_t nbt;
+  int32_t block_size;
+};
+
+// Wavefronts per item; a block is SYM64_WG * i_per_lane particles.  Four
+// wavefronts, not the mixed kernel's eight: at 2 receivers per lane the FP64
+// sweep needs ~168 VGPRs, so a CU holds 3 wavefronts per SIMD, which only
+// 4-wavefront items can fill (8-wavefront items leave it at 2).
+constexpr int SYM64_WAVES = 4;
+constexpr int SYM64_WG = SYM64_WAVES * 64;
+
+// receivers per lane 1 or 2
+hipError_t launch_sym64(const SymArgs64& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q,
+                        bool with_phi, hipStream_t s);
+hipError_t launch_sym64_fold(const SymFoldArgs64& a, bool with_phi, hipStream_t s);
+int sym64_blocks_per_cu(int i_per_lane);
+
+}  // namespace ppk

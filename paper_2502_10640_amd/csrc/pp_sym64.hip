@@ -1,0 +1,340 @@
+// pp_sym64.hip -- symmetric FP64 pair sum for gfx950 (the FP64 path's
+// schedule for large bunches).
+//
+// Same method as the mixed symmetric kernel (pp_sym.hip): the pair term of
+// Eq. (A) is antisymmetric, so one reciprocal square root serves the two
+// ordered interactions of an unordered pair.  Items pair a receiver block I (SYM64_WAVES wavefronts, i_per_lane receivers
+// per lane in VGPRs) with a source block J swept in groups of 64 staged in
+// LDS; in step s of a group lane l meets source (l + s) mod 64 and the
+// source-side partial follows its source one lane down per step (two
+// ds_bpermute per double), handed to the source's home lane with two-sum every
+// 16 steps.  r^-3 comes from v_rsq_f64 and one third-order series correction
+// (inv_r3_64).  Items write FP64 partial slots indexed (round, block, side); the
+// fold adds them in round order, so every addition has a fixed order.
+//
+// Positions are the unscaled FP64 state and separations are plain FP64
+// differences (no hi/lo split and no spatial sort are needed at this
+// precision).
+#include "pp_device.h"
+#include "pp_device64.h"
+#include "pp_sym64.h"
+
+#include <cmath>
+
+namespace ppk {
+namespace {
+
+// Out-of-range receivers and sources of a ragged block sit at two distinct far
+// points: their separation to anything is ~1e100, so their terms are below
+// 1e-200 (far under the last bit of any real sum) and no separation is ever
+// zero (r2 = 0 would give y = inf and e = 1 - 0 * inf = NaN in inv_r3_64).
+constexpr double FAR_RECV = 1e100;
+constexpr double FAR_SRC = -1e100;
+
+__device__ __forceinline__ double lane_read64(double v, int src_lane) {
+  // value of v in lane src_lane (two ds_bpermute, LDS crossbar only)
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(bits & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(bits >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ void two_sum_pair64(double& s, double& c, double t, double tc) {
+  two_sum(s, c, t);
+  c += tc;
+}
+
+template <int K, bool UQ, bool PHI, bool DIAG>
+__device__ __forceinline__ void sweep_group64(const double4* __restrict__ sj, int l, int gsel,
+                                              const double (&xi)[K], const double (&yi)[K], const double (&zi)[K],
+                                              const double (&qi)[K], double eps2, double (&ti)[3][K],
+                                              double (&tip)[K], double (&Sj)[4], double (&Cj)[4]) {
+  // aj: plain partial of the source met in this step, (l + s) mod 64; the group
+  // is stored twice in LDS so step s reads entry l + s with no wrap
+  double aj[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < 64; s0 += 16) {
+    const double4* hb = sj + (l + s0);
+#pragma unroll 4
+    for (int u = 0; u < 16; ++u) {
+      const int s = s0 + u;
+      const double4 h = hb[u];
+      double dx[K], dy[K], dz[K], s3[K], inv[K];
+      bool self[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dx[k] = xi[k] - h.x;
+        dy[k] = yi[k] - h.y;
+        dz[k] = zi[k] - h.z;
+        double r2 = fma(dz[k], dz[k], fma(dy[k], dy[k], fma(dx[k], dx[k], eps2)));
+        // self term: receiver group gsel + k meets source lane l at step 0
+        self[k] = DIAG && s == 0 && gsel == k;
+        if (DIAG && self[k]) r2 = 1.0;
+        s3[k] = inv_r3_64<PHI>(r2, inv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double f3 = s3[k];
+        double ph = PHI ? inv[k] : 0.0;
+        if (DIAG && self[k]) { f3 = 0.0; ph = 0.0; }
+        const double fi = UQ ? f3 : h.w * f3;
+        ti[0][k] = fma(dx[k], fi, ti[0][k]);
+        ti[1][k] = fma(dy[k], fi, ti[1][k]);
+        ti[2][k] = fma(dz[k], fi, ti[2][k]);
+        if (PHI) tip[k] += UQ ? ph : h.w * ph;
+        if (!DIAG) {
+          const double fj = UQ ? f3 : qi[k] * f3;
+          aj[0] = fma(-dx[k], fj, aj[0]);
+          aj[1] = fma(-dy[k], fj, aj[1]);
+          aj[2] = fma(-dz[k], fj, aj[2]);
+          if (PHI) aj[3] += UQ ? ph : qi[k] * ph;
+        }
+      }
+      if (!DIAG) {
+        if ((s & 15) == 15) {
+          // lane l receives the partial of source l from lane (l - s) mod 64
+          const int from = (l - s) & 63;
+#pragma unroll
+          for (int q = 0; q < (PHI ? 4 : 3); ++q) {
+            const double m = lane_read64(aj[q], from);
+            two_sum(Sj[q], Cj[q], m);
+            aj[q] = 0.0;
+          }
+        } else {
+          // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
+#pragma unroll
+          for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read64(aj[q], (l + 1) & 63);
+        }
+      }
+    }
+  }
+}
+
+struct SymShared64 {
+  double4 sj[128];               // source group twice: position, normalised charge
+  double xw[SYM64_WAVES][8][64];   // per-wave two-sum pairs for the cross-wave combine
+};
+
+template <int K, bool UQ, bool PHI, bool DIAG>
+__device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& sh) {
+  double4* sj = sh.sj;
+  auto& xw = sh.xw;
+  const BunchDev& B = a.bunches[it.b];
+  const int n = (int)B.n;
+  const int64_t off = B.off;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  constexpr int BS = SYM64_WAVES * 64 * K;
+  const int ibase = it.I * BS, jbase0 = it.J * BS;
+  const double eps2 = B.eps2;
+  const int64_t rho = it.r - a.r0;
+  double* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
+  double* sslot = a.slot + ((rho * a.nbt + B.bbase + it.J) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
+
+  double xi[K], yi[K], zi[K], qi[K];
+  double Si[3][K], Ci[3][K], Sip[K], Cip[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int li = ibase + (w * K + k) * 64 + l;
+    if (li < n) {
+      const int64_t g = off + li;
+      xi[k] = a.x[g]; yi[k] = a.y[g]; zi[k] = a.z[g];
+      qi[k] = UQ ? 1.0 : a.qt[g];
+    } else {
+      xi[k] = yi[k] = zi[k] = FAR_RECV;
+      qi[k] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Si[c][k] = Ci[c][k] = 0.0;
+    Sip[k] = Cip[k] = 0.0;
+  }
+
+  for (int g = 0; g < BS / 64; ++g) {
+    const int jg = jbase0 + g * 64;
+    __syncthreads();  // LDS of the previous group is free
+    if (w == 0) {
+      const int lj = jg + l;
+      double4 v;
+      if (lj < n) {
+        const int64_t gi = off + lj;
+        v = make_double4(a.x[gi], a.y[gi], a.z[gi], UQ ? 1.0 : a.qt[gi]);
+      } else {
+        v = make_double4(FAR_SRC, FAR_SRC, FAR_SRC, 0.0);
+      }
+      sj[l] = v;
+      sj[l + 64] = v;
+    }
+    __syncthreads();
+
+    double ti[3][K], tip[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.0; }
+    double Sj[4] = {0.0, 0.0, 0.0, 0.0}, Cj[4] = {0.0, 0.0, 0.0, 0.0};
+    // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
+    sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, Sj, Cj);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      two_sum(Si[0][k], Ci[0][k], ti[0][k]);
+      two_sum(Si[1][k], Ci[1][k], ti[1][k]);
+      two_sum(Si[2][k], Ci[2][k], ti[2][k]);
+      if (PHI) two_sum(Sip[k], Cip[k], tip[k]);
+    }
+    if (!DIAG) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xw[w][q][l] = Sj[q];
+        xw[w][4 + q][l] = Cj[q];
+      }
+      __syncthreads();
+      // one thread per (source, component): waves 0-3 combine the waves' pairs
+      // in wave order and store the source-side partial
+      const int q = tid >> 6;
+      if (q < (PHI ? 4 : 3)) {
+        double S = xw[0][q][l], C = xw[0][4 + q][l];
+        for (int ww = 1; ww < SYM64_WAVES; ++ww) two_sum_pair64(S, C, xw[ww][q][l], xw[ww][4 + q][l]);
+        if (jg + l < n) {
+          const int o = g * 64 + l;
+          sslot[(q < 3 ? q : 6) * BS + o] = S;
+          sslot[(q < 3 ? 3 + q : 7) * BS + o] = C;
+        }
+      }
+    }
+  }
+
+  // receiver-side partial
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int o = (w * K + k) * 64 + l;
+    if (ibase + o >= n) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rslot[c * BS + o] = Si[c][k];
+      rslot[(3 + c) * BS + o] = Ci[c][k];
+    }
+    if (PHI) {
+      rslot[6 * BS + o] = Sip[k];
+      rslot[7 * BS + o] = Cip[k];
+    }
+  }
+}
+
+template <int K, bool UQ, bool PHI>
+__global__ __launch_bounds__(SYM64_WG) void pair_sym64_kernel(SymArgs64 a, int32_t first) {
+  __shared__ SymShared64 sh;
+  const SymItem it = a.items[first + blockIdx.x];
+  if (it.r == 0)
+    sym_item64<K, UQ, PHI, true>(a, it, sh);
+  else
+    sym_item64<K, UQ, PHI, false>(a, it, sh);
+}
+
+template <int K, bool UQ, bool PHI>
+hipError_t go_sym64(const SymArgs64& a, int32_t first, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL((pair_sym64_kernel<K, UQ, PHI>), dim3(count), dim3(SYM64_WG), 0, s, a, first);
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t go_sym64_k(const SymArgs64& a, int32_t first, int32_t count, bool uq, bool phi, hipStream_t s) {
+  if (uq) return phi ? go_sym64<K, true, true>(a, first, count, s) : go_sym64<K, true, false>(a, first, count, s);
+  return phi ? go_sym64<K, false, true>(a, first, count, s) : go_sym64<K, false, false>(a, first, count, s);
+}
+
+// One thread per position: adds the slots of rounds [r0, r1) in round order
+// to the accumulators; round 0 (diagonal items) starts them.
+template <bool PHI>
+__global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_total) return;
+  const int b = a.bid[p];
+  if (b < 0) return;
+  const BunchDev& B = a.bunches[b];
+  const int BS = a.block_size;
+  const int l = (int)(p - B.off);
+  const int X = l / BS, o = l - X * BS;
+  const int nbk = (int)((B.n + BS - 1) / BS), half = nbk / 2;
+  constexpr int NQ = PHI ? 4 : 3;
+  const int64_t P = a.n_total;
+  double rs[NQ], rc[NQ], ss[NQ], sc[NQ];
+  // accumulator planes of component q: receiver S, C and source S, C
+  auto pl = [](int q, int k) { return q < 3 ? q + 3 * k : 12 + k; };
+  if (a.r0 == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rs[q] = rc[q] = ss[q] = sc[q] = 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      rs[q] = a.acc[pl(q, 0) * P + p];
+      rc[q] = a.acc[pl(q, 1) * P + p];
+      ss[q] = a.acc[pl(q, 2) * P + p];
+      sc[q] = a.acc[pl(q, 3) * P + p];
+    }
+  }
+  const int64_t sl = (int64_t)SLOT_PLANES * BS;
+  for (int r = a.r0; r < a.r1; ++r) {
+    const double* base = a.slot + ((int64_t)(r - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+    if (r == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        rs[q] = base[(q < 3 ? q : 6) * BS];
+        rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+      }
+      continue;
+    }
+    if (r > half) continue;  // the bunch has no item in this round
+    // receiver side: item (X, X + r); source side: item (X - r, X); with an even
+    // block count the round r = nbk / 2 holds only the items with I < nbk / 2
+    const bool has_r = !(2 * r == nbk && X >= half);
+    const int js = X - r < 0 ? X - r + nbk : X - r;
+    const bool has_s = !(2 * r == nbk && js >= half);
+    if (has_r) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        two_sum_pair64(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+    }
+    if (has_s) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        two_sum_pair64(ss[q], sc[q], base[sl + (q < 3 ? q : 6) * BS], base[sl + (q < 3 ? 3 + q : 7) * BS]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    a.acc[pl(q, 0) * P + p] = rs[q];
+    a.acc[pl(q, 1) * P + p] = rc[q];
+    a.acc[pl(q, 2) * P + p] = ss[q];
+    a.acc[pl(q, 3) * P + p] = sc[q];
+  }
+}
+
+}  // namespace
+
+int sym64_blocks_per_cu(int i_per_lane) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (i_per_lane) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym64_kernel<1, true, false>, SYM64_WG, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym64_kernel<2, true, false>, SYM64_WG, 0); break;
+    default: break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_sym64_fold(const SymFoldArgs64& a, bool with_phi, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.n_total + 255) / 256);
+  if (with_phi)
+    hipLaunchKernelGGL(sym64_fold_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(sym64_fold_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym64(const SymArgs64& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q,
+                        bool with_phi, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (i_per_lane) {
+    case 1: return go_sym64_k<1>(a, first, count, uniform_q, with_phi, s);
+    case 2: return go_sym64_k<2>(a, first, count, uniform_q, with_phi, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ppk

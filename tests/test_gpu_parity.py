@@ -164,13 +164,14 @@ DIAG_VECTORS = ("com", "com_velocity", "emittance", "emittance_centered", "x_rms
 
 
 DIAG_TUNING = {"fp64": None, "mixed": None,
-               "mixed_symmetric_far": {"symmetric": 1, "i_per_lane": 1, "far_split": 3}}
+               "mixed_symmetric_far": {"symmetric": 1, "i_per_lane": 1, "far_split": 3},
+               "fp64_symmetric": {"symmetric": 1, "i_per_lane": 1}}
 
 
 @pytest.mark.parametrize("variant", list(DIAG_TUNING))
 def test_diagnostics_parity(orc, variant):
     """GPU diagnostics against the oracle's on the GPU's own state."""
-    prec = "fp64" if variant == "fp64" else "mixed"
+    prec = "fp64" if variant.startswith("fp64") else "mixed"
     b = wl.workload("gaussian_65536", n_override=4096)[0]
     say(f"diagnostics {variant} n={b.n}")
     with Sim([b], prec, tuning=DIAG_TUNING[variant]) as sim:
@@ -242,6 +243,10 @@ def test_batch_equals_separate_contexts_bitwise(prec):
 def test_symmetric_far_batch_equals_separate_contexts_bitwise():
     # the sort keys, the coordinate bound, the boxes and the fold are all per bunch
     _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "far_split": 3})
+
+
+def test_fp64_symmetric_batch_equals_separate_contexts_bitwise():
+    _batch_equals_separate("fp64", {"i_per_lane": 1, "symmetric": 1, "far_split": 0})
 
 
 def _batch_equals_separate(prec, tuning):
@@ -337,24 +342,27 @@ def test_invalid_tuning_rejected():
     say("invalid tuning")
     with Sim([b], "fp64") as sim:
         for bad in ({"i_per_lane": 3}, {"i_per_lane": 8}, {"sum_tile": 48}, {"grid_per_cu": 0},
-                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}):
+                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}, {"symmetric": 1, "i_per_lane": 4}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
             assert e.value.status == pp.PP_ERR_INVALID_ARG
         sim.push(1)
 
 
-def test_full_size_sampled_parity_cold_sphere_1m(orc):
-    """The 1 048 576-particle cold sphere in the benchmark's configuration:
-    the GPU field at 384 sampled receivers against the oracle."""
+@pytest.mark.parametrize("prec", PRECS)
+def test_full_size_sampled_parity_cold_sphere_1m(orc, prec):
+    """The 1 048 576-particle cold sphere in the benchmark's configuration
+    (default tiling of each precision): the GPU field at 384 sampled receivers
+    against the oracle."""
     b = wl.workload("cold_sphere_1m")[0]
     rng = np.random.default_rng(99)
     recv = np.sort(rng.choice(b.n, 384, replace=False))
-    say(f"full size sampled parity cold_sphere_1m mixed n={b.n}")
-    with Sim([b], "mixed") as sim:
+    say(f"full size sampled parity cold_sphere_1m {prec} n={b.n}")
+    with Sim([b], prec) as sim:
+        print(f"    tuning {sim.tuning()}", flush=True)
         got = gpu_field(sim, sl=recv)
     ref = oracle_field(orc, b, recv=recv)
-    check_field(got, ref, TOL["mixed"], "cold_sphere_1m/mixed sampled")
+    check_field(got, ref, TOL[prec], f"cold_sphere_1m/{prec} sampled")
 
 
 # ---------------------------------------------------------------------------
@@ -366,26 +374,27 @@ def _sym_bunches():
             mixed_charge_bunch(1500, seed=5), wl.workload("cold_sphere_2048", n_override=5)[0]]
 
 
-@pytest.mark.parametrize("K", [1, 2, 4])
-def test_symmetric_field_parity(orc, K):
+@pytest.mark.parametrize("prec,K", [("mixed", 1), ("mixed", 2), ("mixed", 4), ("fp64", 1), ("fp64", 2)])
+def test_symmetric_field_parity(orc, prec, K):
     bunches = _sym_bunches()
-    say(f"symmetric field K={K} sizes={[b.n for b in bunches]}")
-    with Sim(bunches, "mixed", tuning={"symmetric": 1, "i_per_lane": K}) as sim:
+    say(f"symmetric field {prec} K={K} sizes={[b.n for b in bunches]}")
+    with Sim(bunches, prec, tuning={"symmetric": 1, "i_per_lane": K, "far_split": 0}) as sim:
         assert sim.tuning()["symmetric"] == 1
         full = gpu_field(sim)
         for k, b in enumerate(bunches):
             sl = sim.bunch_slice(k)
             got = {key: v[sl] for key, v in full.items()}
-            check_field(got, oracle_field(orc, b), TOL["mixed"], f"sym K={K} n={b.n}")
+            check_field(got, oracle_field(orc, b), TOL[prec], f"sym {prec} K={K} n={b.n}")
 
 
-def test_symmetric_push_graph_and_trajectory(orc):
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_push_graph_and_trajectory(orc, prec):
     b = wl.workload("gaussian_65536", n_override=2500)[0]
-    say("symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps")
+    say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}")
     tun = {"symmetric": 1, "i_per_lane": 1, "graph_steps": 3}
     res = []
     for mode in ("push", "graph"):
-        with Sim([b], "mixed", tuning=tun) as sim:
+        with Sim([b], prec, tuning=tun) as sim:
             if mode == "push":
                 sim.push(8)
             else:
@@ -398,15 +407,16 @@ def test_symmetric_push_graph_and_trajectory(orc):
     v_rms = math.sqrt(np.mean(s.vx ** 2 + s.vy ** 2 + s.vz ** 2))
     ev = max(np.abs(res[0][k] - getattr(s, k)).max() for k in ("vx", "vy", "vz")) / v_rms
     print(f"    symmetric trajectory: max|dv|/v_rms={ev:.3e}", flush=True)
-    assert ev <= 1e-6
+    assert ev <= (1e-11 if prec == "fp64" else 1e-6)
 
 
-def test_symmetric_equals_itself_run_to_run():
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_equals_itself_run_to_run(prec):
     b = wl.workload("cold_sphere_2048")[0]
-    say("symmetric run-to-run bitwise")
+    say(f"symmetric run-to-run bitwise {prec}")
     outs = []
     for _ in range(2):
-        with Sim([b], "mixed", tuning={"symmetric": 1, "i_per_lane": 2}) as sim:
+        with Sim([b], prec, tuning={"symmetric": 1, "i_per_lane": 2}) as sim:
             outs.append(gpu_field(sim))
     for k in outs[0]:
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
@@ -493,6 +503,7 @@ def test_far_split_tuning_rules():
     with Sim([b], "fp64") as sim:
         with pytest.raises(pp.PPError):
             sim.set_tuning(symmetric=1, i_per_lane=1, far_split=1)
+        sim.set_tuning(symmetric=1, i_per_lane=2, far_split=0)   # symmetric FP64 has no far split
 
 
 def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatch):
@@ -531,13 +542,14 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
 # the other benchmark workloads at full size, default tilings (as bench.py runs them)
 # ---------------------------------------------------------------------------
 
-def test_full_size_parity_gaussian_65536(orc):
+@pytest.mark.parametrize("prec", PRECS)
+def test_full_size_parity_gaussian_65536(orc, prec):
     b = wl.workload("gaussian_65536")[0]
-    say(f"full size parity gaussian_65536 mixed n={b.n} (every receiver)")
-    with Sim([b], "mixed") as sim:
+    say(f"full size parity gaussian_65536 {prec} n={b.n} (every receiver)")
+    with Sim([b], prec) as sim:
         print(f"    tuning {sim.tuning()}", flush=True)
         got = gpu_field(sim)
-    check_field(got, oracle_field(orc, b), TOL["mixed"], "gaussian_65536/mixed")
+    check_field(got, oracle_field(orc, b), TOL[prec], f"gaussian_65536/{prec}")
 
 
 def test_full_size_sampled_parity_ellipsoid_4m(orc):
