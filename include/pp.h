@@ -132,10 +132,10 @@ typedef struct {
   int32_t graph_steps;   /* steps captured per hipGraph with PP_GRAPH, 1..1024   */
   int32_t symmetric;     /* 1 evaluates each unordered pair once (Newton's
                             third law, Eq. (A) antisymmetry) in rounds of block
-                            pairs, i_per_lane 1, 2 or 4 for PP_MIXED (blocks of
-                            512 i_per_lane particles) and 1 or 2 for PP_FP64
-                            (blocks of 256 i_per_lane particles); 0 evaluates
-                            every ordered pair in the ordered-pair kernel       */
+                            pairs, i_per_lane 1, 2 or 4 (blocks of 512
+                            i_per_lane particles for PP_MIXED, 256 i_per_lane
+                            for PP_FP64); 0 evaluates every ordered pair in
+                            the ordered-pair kernel                             */
   int32_t far_split;     /* PP_MIXED symmetric only: 0 keeps the hi/lo separations of
                             Sec. 3 for every pair; f in 1..4 orders each bunch
                             along a Morton curve every evaluation and uses plain

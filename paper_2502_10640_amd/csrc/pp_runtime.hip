@@ -641,8 +641,8 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.grid_per_cu < 1 || t.grid_per_cu > 16) return false;
   if (t.graph_steps < 1 || t.graph_steps > 1024) return false;
   if (t.symmetric != 0 && t.symmetric != 1) return false;
-  // symmetric: 1, 2 or 4 receivers per lane (FP64: 1 or 2); the near/far split is mixed only
-  if (t.symmetric && (k == 8 || (!mixed && k > 2))) return false;
+  // symmetric: 1, 2 or 4 receivers per lane; the near/far split is mixed only
+  if (t.symmetric && k == 8) return false;
   // far_split <= 4 keeps the per-term bound 2 sqrt(3) 2^-23 2^f at 6.6e-6, inside the mixed tolerance
   if (t.far_split < 0 || t.far_split > 4 || (t.far_split > 0 && (!t.symmetric || !mixed))) return false;
   return true;
@@ -653,10 +653,10 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
 // cheaper than the ordered-pair kernel.  Costs in units of one ordered pair in
 // the ordered kernel of the same precision, from measurements on MI355X: an
 // off-diagonal unordered pair 1.02, a diagonal-block pair 0.6, times a
-// per-variant factor (mixed: 1.0 at 4 receivers per lane, 1.1 at 2; FP64: 1.55
-// at 2, the FP64 sweep gaining less over its ordered kernel because the
-// source-side rotation is two ds_bpermute per double and the fold of FP64
-// slots costs ~4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
+// per-variant factor (mixed: 1.0 at 4 receivers per lane, 1.1 at 2; FP64: 1.28
+// at 4, 1.51 at 2, the FP64 sweep gaining less over its ordered kernel because
+// its r^-3 costs more relative to the rest of a pair and the fold of FP64
+// slots costs 2-4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
 // is left to the autotuner.  Padded blocks are paid in full, and the cost is
 // divided by the fill of the last wave of workgroups (items over resident
 // slots times the waves they need).
@@ -680,7 +680,8 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
     vars.push_back({4, (double)ppk::SYM_WG * 4, 1.0, ppk::sym_blocks_per_cu(4)});
     vars.push_back({2, (double)ppk::SYM_WG * 2, 1.1, ppk::sym_blocks_per_cu(2)});
   } else {
-    vars.push_back({2, (double)ppk::SYM64_WG * 2, 1.55, ppk::sym64_blocks_per_cu(2)});
+    vars.push_back({4, (double)ppk::SYM64_WG * 4, 1.28, ppk::sym64_blocks_per_cu(4)});
+    vars.push_back({2, (double)ppk::SYM64_WG * 2, 1.51, ppk::sym64_blocks_per_cu(2)});
   }
   double best = ordered;
   for (const Variant& v : vars) {

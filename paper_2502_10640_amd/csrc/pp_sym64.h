@@ -30,13 +30,13 @@ struct SymFoldArgs64 {
 };
 
 // Wavefronts per item; a block is SYM64_WG * i_per_lane particles.  Four
-// wavefronts, not the mixed kernel's eight: at 2 receivers per lane the FP64
-// sweep needs ~168 VGPRs, so a CU holds 3 wavefronts per SIMD, which only
-// 4-wavefront items can fill (8-wavefront items leave it at 2).
+// wavefronts, not the mixed kernel's eight: the 4-receiver FP64 sweep needs
+// 160 VGPRs, so a CU holds 3 wavefronts per SIMD, which only 4-wavefront items
+// can fill (8-wavefront items leave it at 2 and measured 5% slower at 1M).
 constexpr int SYM64_WAVES = 4;
 constexpr int SYM64_WG = SYM64_WAVES * 64;
 
-// receivers per lane 1 or 2
+// receivers per lane 1, 2 or 4
 hipError_t launch_sym64(const SymArgs64& a, int32_t first, int32_t count, int i_per_lane, bool uniform_q,
                         bool with_phi, hipStream_t s);
 hipError_t launch_sym64_fold(const SymFoldArgs64& a, bool with_phi, hipStream_t s);

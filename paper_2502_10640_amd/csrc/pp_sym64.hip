@@ -7,8 +7,8 @@
 // per lane in VGPRs) with a source block J swept in groups of 64 staged in
 // LDS; in step s of a group lane l meets source (l + s) mod 64 and the
 // source-side partial follows its source one lane down per step (two
-// ds_bpermute per double), handed to the source's home lane with two-sum every
-// 16 steps.  r^-3 comes from v_rsq_f64 and one third-order series correction
+// ds_bpermute per double), arriving at the source's home lane after the 64th
+// step.  r^-3 comes from v_rsq_f64 and one third-order series correction
 // (inv_r3_64).  Items write FP64 partial slots indexed (round, block, side); the
 // fold adds them in round order, so every addition has a fixed order.
 //
@@ -48,70 +48,57 @@ template <int K, bool UQ, bool PHI, bool DIAG>
 __device__ __forceinline__ void sweep_group64(const double4* __restrict__ sj, int l, int gsel,
                                               const double (&xi)[K], const double (&yi)[K], const double (&zi)[K],
                                               const double (&qi)[K], double eps2, double (&ti)[3][K],
-                                              double (&tip)[K], double (&Sj)[4], double (&Cj)[4]) {
-  // aj: plain partial of the source met in this step, (l + s) mod 64; the group
-  // is stored twice in LDS so step s reads entry l + s with no wrap
-  double aj[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int s0 = 0; s0 < 64; s0 += 16) {
-    const double4* hb = sj + (l + s0);
+                                              double (&tip)[K], double (&aj)[4]) {
+  // aj: plain partial of the source met in step s, (l + s) mod 64, which moves
+  // one lane down after every step; after the 64 steps lane l holds the whole
+  // group's partial of its own source l (64 terms in a plain FP64 sum, as the
+  // receiver side's tile sum).  The group is stored twice in LDS so step s
+  // reads entry l + s with no wrap.
 #pragma unroll 4
-    for (int u = 0; u < 16; ++u) {
-      const int s = s0 + u;
-      const double4 h = hb[u];
-      double dx[K], dy[K], dz[K], s3[K], inv[K];
-      bool self[K];
+  for (int s = 0; s < 64; ++s) {
+    const double4 h = sj[l + s];
+    double dx[K], dy[K], dz[K], s3[K], inv[K];
+    bool self[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        dx[k] = xi[k] - h.x;
-        dy[k] = yi[k] - h.y;
-        dz[k] = zi[k] - h.z;
-        double r2 = fma(dz[k], dz[k], fma(dy[k], dy[k], fma(dx[k], dx[k], eps2)));
-        // self term: receiver group gsel + k meets source lane l at step 0
-        self[k] = DIAG && s == 0 && gsel == k;
-        if (DIAG && self[k]) r2 = 1.0;
-        s3[k] = inv_r3_64<PHI>(r2, inv[k]);
-      }
+    for (int k = 0; k < K; ++k) {
+      dx[k] = xi[k] - h.x;
+      dy[k] = yi[k] - h.y;
+      dz[k] = zi[k] - h.z;
+      double r2 = fma(dz[k], dz[k], fma(dy[k], dy[k], fma(dx[k], dx[k], eps2)));
+      // self term: receiver group gsel + k meets source lane l at step 0
+      self[k] = DIAG && s == 0 && gsel == k;
+      if (DIAG && self[k]) r2 = 1.0;
+      s3[k] = inv_r3_64<PHI>(r2, inv[k]);
+    }
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        double f3 = s3[k];
-        double ph = PHI ? inv[k] : 0.0;
-        if (DIAG && self[k]) { f3 = 0.0; ph = 0.0; }
-        const double fi = UQ ? f3 : h.w * f3;
-        ti[0][k] = fma(dx[k], fi, ti[0][k]);
-        ti[1][k] = fma(dy[k], fi, ti[1][k]);
-        ti[2][k] = fma(dz[k], fi, ti[2][k]);
-        if (PHI) tip[k] += UQ ? ph : h.w * ph;
-        if (!DIAG) {
-          const double fj = UQ ? f3 : qi[k] * f3;
-          aj[0] = fma(-dx[k], fj, aj[0]);
-          aj[1] = fma(-dy[k], fj, aj[1]);
-          aj[2] = fma(-dz[k], fj, aj[2]);
-          if (PHI) aj[3] += UQ ? ph : qi[k] * ph;
-        }
-      }
+    for (int k = 0; k < K; ++k) {
+      double f3 = s3[k];
+      double ph = PHI ? inv[k] : 0.0;
+      if (DIAG && self[k]) { f3 = 0.0; ph = 0.0; }
+      const double fi = UQ ? f3 : h.w * f3;
+      ti[0][k] = fma(dx[k], fi, ti[0][k]);
+      ti[1][k] = fma(dy[k], fi, ti[1][k]);
+      ti[2][k] = fma(dz[k], fi, ti[2][k]);
+      if (PHI) tip[k] += UQ ? ph : h.w * ph;
       if (!DIAG) {
-        if ((s & 15) == 15) {
-          // lane l receives the partial of source l from lane (l - s) mod 64
-          const int from = (l - s) & 63;
-#pragma unroll
-          for (int q = 0; q < (PHI ? 4 : 3); ++q) {
-            const double m = lane_read64(aj[q], from);
-            two_sum(Sj[q], Cj[q], m);
-            aj[q] = 0.0;
-          }
-        } else {
-          // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
-#pragma unroll
-          for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read64(aj[q], (l + 1) & 63);
-        }
+        const double fj = UQ ? f3 : qi[k] * f3;
+        aj[0] = fma(-dx[k], fj, aj[0]);
+        aj[1] = fma(-dy[k], fj, aj[1]);
+        aj[2] = fma(-dz[k], fj, aj[2]);
+        if (PHI) aj[3] += UQ ? ph : qi[k] * ph;
       }
+    }
+    if (!DIAG) {
+      // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
+#pragma unroll
+      for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read64(aj[q], (l + 1) & 63);
     }
   }
 }
 
 struct SymShared64 {
-  double4 sj[128];               // source group twice: position, normalised charge
-  double xw[SYM64_WAVES][8][64];   // per-wave two-sum pairs for the cross-wave combine
+  double4 sj[128];                 // source group twice: position, normalised charge
+  double xw[SYM64_WAVES][4][64];   // per-wave source-side partials for the cross-wave combine
 };
 
 template <int K, bool UQ, bool PHI, bool DIAG>
@@ -167,9 +154,9 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     double ti[3][K], tip[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.0; }
-    double Sj[4] = {0.0, 0.0, 0.0, 0.0}, Cj[4] = {0.0, 0.0, 0.0, 0.0};
+    double aj[4] = {0.0, 0.0, 0.0, 0.0};
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
-    sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, Sj, Cj);
+    sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       two_sum(Si[0][k], Ci[0][k], ti[0][k]);
@@ -179,17 +166,14 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     }
     if (!DIAG) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xw[w][q][l] = Sj[q];
-        xw[w][4 + q][l] = Cj[q];
-      }
+      for (int q = 0; q < (PHI ? 4 : 3); ++q) xw[w][q][l] = aj[q];
       __syncthreads();
-      // one thread per (source, component): waves 0-3 combine the waves' pairs
-      // in wave order and store the source-side partial
+      // one thread per (source, component): waves 0-3 add the waves' partials
+      // in wave order with two-sum and store the source-side (S, C)
       const int q = tid >> 6;
       if (q < (PHI ? 4 : 3)) {
-        double S = xw[0][q][l], C = xw[0][4 + q][l];
-        for (int ww = 1; ww < SYM64_WAVES; ++ww) two_sum_pair64(S, C, xw[ww][q][l], xw[ww][4 + q][l]);
+        double S = xw[0][q][l], C = 0.0;
+        for (int ww = 1; ww < SYM64_WAVES; ++ww) two_sum(S, C, xw[ww][q][l]);
         if (jg + l < n) {
           const int o = g * 64 + l;
           sslot[(q < 3 ? q : 6) * BS + o] = S;
@@ -313,6 +297,7 @@ int sym64_blocks_per_cu(int i_per_lane) {
   switch (i_per_lane) {
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym64_kernel<1, true, false>, SYM64_WG, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym64_kernel<2, true, false>, SYM64_WG, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pair_sym64_kernel<4, true, false>, SYM64_WG, 0); break;
     default: break;
   }
   return (e == hipSuccess && n > 0) ? n : 1;
@@ -333,6 +318,7 @@ hipError_t launch_sym64(const SymArgs64& a, int32_t first, int32_t count, int i_
   switch (i_per_lane) {
     case 1: return go_sym64_k<1>(a, first, count, uniform_q, with_phi, s);
     case 2: return go_sym64_k<2>(a, first, count, uniform_q, with_phi, s);
+    case 4: return go_sym64_k<4>(a, first, count, uniform_q, with_phi, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -342,7 +342,7 @@ def test_invalid_tuning_rejected():
     say("invalid tuning")
     with Sim([b], "fp64") as sim:
         for bad in ({"i_per_lane": 3}, {"i_per_lane": 8}, {"sum_tile": 48}, {"grid_per_cu": 0},
-                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}, {"symmetric": 1, "i_per_lane": 4}):
+                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}, {"symmetric": 1, "i_per_lane": 8}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
             assert e.value.status == pp.PP_ERR_INVALID_ARG
@@ -374,7 +374,7 @@ def _sym_bunches():
             mixed_charge_bunch(1500, seed=5), wl.workload("cold_sphere_2048", n_override=5)[0]]
 
 
-@pytest.mark.parametrize("prec,K", [("mixed", 1), ("mixed", 2), ("mixed", 4), ("fp64", 1), ("fp64", 2)])
+@pytest.mark.parametrize("prec,K", [("mixed", 1), ("mixed", 2), ("mixed", 4), ("fp64", 1), ("fp64", 2), ("fp64", 4)])
 def test_symmetric_field_parity(orc, prec, K):
     bunches = _sym_bunches()
     say(f"symmetric field {prec} K={K} sizes={[b.n for b in bunches]}")
