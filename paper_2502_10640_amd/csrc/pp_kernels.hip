@@ -300,11 +300,11 @@ __device__ __forceinline__ double drift1(double r, double v, double acc, double 
 }
 
 // mirror of one particle: u = (r - origin) * scale, hi = fl32(u), lo = fl32(u - hi)
-__device__ __forceinline__ void mirror1(const BunchDev& B, int64_t i, double x, double y, double z, float* xh,
-                                        float* yh, float* zh, float* xl, float* yl, float* zl) {
-  const double ux = (x - B.origin[0]) * B.scale;
-  const double uy = (y - B.origin[1]) * B.scale;
-  const double uz = (z - B.origin[2]) * B.scale;
+__device__ __forceinline__ void mirror1(double ox, double oy, double oz, double scale, int64_t i, double x, double y,
+                                        double z, float* xh, float* yh, float* zh, float* xl, float* yl, float* zl) {
+  const double ux = (x - ox) * scale;
+  const double uy = (y - oy) * scale;
+  const double uz = (z - oz) * scale;
   const float hx = (float)ux, hy = (float)uy, hz = (float)uz;
   xh[i] = hx; yh[i] = hy; zh[i] = hz;
   xl[i] = (float)(ux - (double)hx);
@@ -320,6 +320,8 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
   const int b = a.bid[i];
   if (b < 0) return;
   const BunchDev& B = a.bunches[b];
+  // bunch constants before the stores of x (which would otherwise order these loads after them)
+  const double ox = B.origin[0], oy = B.origin[1], oz = B.origin[2], scale = B.scale;
   double x = a.x[i], y = a.y[i], z = a.z[i];
   if (DRIFT) {
     const double dt = B.dt;
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     z = drift1(z, a.vz[i], a.az[i], dt);
     a.x[i] = x; a.y[i] = y; a.z[i] = z;
   }
-  if (MIXED) mirror1(B, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
+  if (MIXED) mirror1(ox, oy, oz, scale, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +359,9 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   const int b = a.bid[i];
   if (b < 0) return;
   const BunchDev& B = a.bunches[b];
-  const int64_t li = i - B.off;
+  // the bunch fields the chunk loop needs, read together
+  const int64_t li = i - B.off, bn = B.n, pbase = B.pbase;
+  const int n_chunks = a.sym ? 0 : B.n_chunks;
   const bool want_phi = (MODE == FIN_FIELD) && a.phi != nullptr;
   double ex = 0.0, ey = 0.0, ez = 0.0, ph = 0.0;
   if (!MIXED && a.sym) {
@@ -381,8 +385,8 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
   }
   // this lane's chunks in chunk order
 #pragma unroll 4
-  for (int c = t; c < (a.sym ? 0 : B.n_chunks); c += L) {
-    const int64_t s = B.pbase + (int64_t)c * B.n + li;
+  for (int c = t; c < n_chunks; c += L) {
+    const int64_t s = pbase + (int64_t)c * bn + li;
     if (MIXED) {
       ex += (double)a.pf[0 * a.P + s] + (double)a.pf[3 * a.P + s];
       ey += (double)a.pf[1 * a.P + s] + (double)a.pf[4 * a.P + s];
@@ -405,27 +409,43 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
     }
     if (t != 0) return;
   }
-  ex *= B.kE; ey *= B.kE; ez *= B.kE;
+  // Everything the update reads, loaded before its first store: read after
+  // them, the loads of x would wait for the stores of v and the bunch
+  // constants for the stores of x (the compiler cannot rule out aliasing),
+  // each a further round trip to memory.
+  const double dt = B.dt, kE = B.kE;
+  double ox = 0.0, oy = 0.0, oz = 0.0, scale = 0.0;
+  double qi = 0.0, mi = 1.0, v0x = 0.0, v0y = 0.0, v0z = 0.0, a0x = 0.0, a0y = 0.0, a0z = 0.0;
+  double rx = 0.0, ry = 0.0, rz = 0.0;
+  if (MODE != FIN_FIELD) { qi = a.q[i]; mi = a.m[i]; }
+  if (MODE == FIN_KICK || MODE == FIN_KICK_DRIFT) {
+    v0x = a.vx[i]; v0y = a.vy[i]; v0z = a.vz[i];
+    a0x = a.ax[i]; a0y = a.ay[i]; a0z = a.az[i];
+  }
+  if (MODE == FIN_KICK_DRIFT) {
+    rx = a.x[i]; ry = a.y[i]; rz = a.z[i];
+    if (MIXED) { ox = B.origin[0]; oy = B.origin[1]; oz = B.origin[2]; scale = B.scale; }
+  }
+  ex *= kE; ey *= kE; ez *= kE;
   if (MODE == FIN_FIELD) {
     if (a.ex) { a.ex[i] = ex; a.ey[i] = ey; a.ez[i] = ez; }
     if (want_phi) a.phi[i] = ph * B.kPhi;
     return;
   }
-  const double qm = a.q[i] / a.m[i];
+  const double qm = qi / mi;
   const double nax = ex * qm, nay = ey * qm, naz = ez * qm;
   if (MODE == FIN_KICK || MODE == FIN_KICK_DRIFT) {
-    const double dt = B.dt;
-    const double vx = kick1(a.vx[i], a.ax[i], nax, dt);
-    const double vy = kick1(a.vy[i], a.ay[i], nay, dt);
-    const double vz = kick1(a.vz[i], a.az[i], naz, dt);
+    const double vx = kick1(v0x, a0x, nax, dt);
+    const double vy = kick1(v0y, a0y, nay, dt);
+    const double vz = kick1(v0z, a0z, naz, dt);
     a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
     if (MODE == FIN_KICK_DRIFT) {
       // the next step's drift (Eq. (G)) with the velocity and acceleration just stored
-      const double x = drift1(a.x[i], vx, nax, dt);
-      const double y = drift1(a.y[i], vy, nay, dt);
-      const double z = drift1(a.z[i], vz, naz, dt);
+      const double x = drift1(rx, vx, nax, dt);
+      const double y = drift1(ry, vy, nay, dt);
+      const double z = drift1(rz, vz, naz, dt);
       a.x[i] = x; a.y[i] = y; a.z[i] = z;
-      if (MIXED) mirror1(B, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
+      if (MIXED) mirror1(ox, oy, oz, scale, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
     }
   }
   a.ax[i] = nax; a.ay[i] = nay; a.az[i] = naz;

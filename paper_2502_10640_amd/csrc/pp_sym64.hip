@@ -25,11 +25,15 @@ namespace ppk {
 namespace {
 
 // Out-of-range receivers and sources of a ragged block sit at two distinct far
-// points: their separation to anything is ~1e100, so their terms are below
-// 1e-200 (far under the last bit of any real sum) and no separation is ever
-// zero (r2 = 0 would give y = inf and e = 1 - 0 * inf = NaN in inv_r3_64).
-constexpr double FAR_RECV = 1e100;
-constexpr double FAR_SRC = -1e100;
+// points, +-1e149 on every axis, with charge weight 0.  Any separation they
+// take part in has r2 ~ 1e299: finite and never zero (r2 = 0 would give
+// y = inf and e = 1 - 0 * inf = NaN in inv_r3_64), with y ~ 1e-150 and
+// y^3 ~ 1e-449, which underflows to exactly 0, so every field term of a padded
+// particle is an exact zero without the weight.  Only its potential term
+// (y ~ 1e-150) needs the weight: with uniform charges the items that contain
+// padding and want the potential take the weighted sweep.
+constexpr double FAR_RECV = 1e149;
+constexpr double FAR_SRC = -1e149;
 
 __device__ __forceinline__ double lane_read64(double v, int src_lane) {
   // value of v in lane src_lane (two ds_bpermute, LDS crossbar only)
@@ -111,6 +115,7 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   constexpr int BS = SYM64_WAVES * 64 * K;
   const int ibase = it.I * BS, jbase0 = it.J * BS;
+  const bool pad = (n - ibase < BS) || (n - jbase0 < BS);  // a ragged last block takes part
   const double eps2 = B.eps2;
   const int64_t rho = it.r - a.r0;
   double* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
@@ -156,7 +161,10 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.0; }
     double aj[4] = {0.0, 0.0, 0.0, 0.0};
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
-    sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
+    if (UQ && PHI && pad)  // unit weights 1.0 for real particles give the same bits as the uniform path
+      sweep_group64<K, false, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
+    else
+      sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       two_sum(Si[0][k], Ci[0][k], ti[0][k]);

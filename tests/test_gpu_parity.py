@@ -99,12 +99,17 @@ def test_field_parity(orc, prec, case):
 RAGGED = [1, 2, 3, 63, 255, 256, 257, 511, 513, 777, 1025, 2049]
 
 
+RAGGED_TUNINGS = {"ordered": None, "symmetric": {"symmetric": 1, "i_per_lane": 1, "far_split": 0},
+                  "symmetric_k4": {"symmetric": 1, "i_per_lane": 4, "far_split": 0}}
+
+
+@pytest.mark.parametrize("sched", list(RAGGED_TUNINGS))
 @pytest.mark.parametrize("prec", PRECS)
-def test_ragged_batch_with_gaps(orc, prec):
+def test_ragged_batch_with_gaps(orc, prec, sched):
     bunches = [wl.cold_sphere(n, 30e-6 * (1 + k % 3), 2e4 * n, 1e-3, 0.01, 0, seed=300 + k, name=f"r{n}")
                for k, n in enumerate(RAGGED)]
-    say(f"ragged batch {prec} sizes={RAGGED} gap=5")
-    with Sim(bunches, prec, gap=5) as sim:
+    say(f"ragged batch {prec} {sched} sizes={RAGGED} gap=5")
+    with Sim(bunches, prec, gap=5, tuning=RAGGED_TUNINGS[sched]) as sim:
         full = gpu_field(sim)
         for k, b in enumerate(bunches):
             sl = sim.bunch_slice(k)
