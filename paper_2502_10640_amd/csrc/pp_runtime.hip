@@ -9,6 +9,7 @@
 #include "pp.h"
 #include "pp_internal.h"
 #include "pp_sym64.h"
+#include "pp_sort.h"
 
 #include <sys/stat.h>
 
@@ -116,6 +117,7 @@ struct pp_ctx {
   bool sym() const { return tun.symmetric != 0; }
   bool far() const { return mixed() && sym() && tun.far_split > 0; }
   size_t acc_elem() const { return mixed() ? sizeof(float) : sizeof(double); }
+  int key_shift = 30, key_bits = 30;  // sort key layout of the far split (set_sort_bits)
   int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
   // particles per block of the symmetric schedule
   int64_t sym_block() const { return (int64_t)(mixed() ? ppk::SYM_WG : ppk::SYM64_WG) * tun.i_per_lane; }
@@ -201,7 +203,19 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 // ---------------------------------------------------------------------------
 constexpr size_t kSlotBytes = size_t(8) << 30;
 
+// Sort key layout of the far split: each bunch's Morton code is as fine as its
+// own size asks (morton_bits_for), the bunch index sits above the widest code.
+void set_sort_bits(pp_ctx* c) {
+  int bpa = 1;
+  for (const auto& b : c->hb) bpa = std::max(bpa, ppk::morton_bits_for(b.n));
+  int bunch_bits = 0;
+  while ((int64_t(1) << bunch_bits) < c->nb) ++bunch_bits;
+  c->key_shift = 3 * bpa;
+  c->key_bits = c->key_shift + bunch_bits;
+}
+
 pp_status build_sym(pp_ctx* c) {
+  set_sort_bits(c);
   const int64_t BS = c->sym_block();
   std::vector<ppk::SymItem> items;
   std::vector<int64_t> round_first;
@@ -561,9 +575,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
       }
       so.rank = c->rank;
       so.gbox = c->gbox;
-      int bunch_bits = 0;
-      while ((int64_t(1) << bunch_bits) < c->nb) ++bunch_bits;
-      PP_HIP(c, ppk::launch_sort(so, 30 + bunch_bits, c->n_groups, s));
+      PP_HIP(c, ppk::launch_sort_bits(so, c->key_shift, c->key_bits, c->n_groups, s));
       sa.xh = sp[0]; sa.yh = sp[1]; sa.zh = sp[2];
       sa.xl = sp[3]; sa.yl = sp[4]; sa.zl = sp[5];
       sa.qt = sp[6];

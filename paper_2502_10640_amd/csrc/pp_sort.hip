@@ -11,12 +11,19 @@
 // changes by at most 2^-23 (|a| + |b|) / D relative, while closer groups keep
 // the hi/lo separations.  This file computes U, the order and the group boxes.
 //
+// A bunch's Morton code has as many bits per axis as gives it about 8 cells
+// per particle (morton_bits_for: ceil(log2 n / 3) + 1, at most 10), and the
+// bunch index sits just above the widest code of the context, so the sort
+// takes as few 8-bit passes as that allows while a bunch's order depends on
+// the bunch alone.
+//
 // The sort is a stable least-significant-digit radix sort with 8-bit digits:
 // tile histograms (order-free LDS counts), a digit-major exclusive scan, and a
 // scatter that ranks equal digits with wavefront ballots, so the permutation
 // is the same on every run.
 #include "pp_device.h"
 #include "pp_internal.h"
+#include "pp_sort.h"
 
 #include <cmath>
 
@@ -74,13 +81,14 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t quant10(float u, float inv_u) {
-  float t = (u * inv_u + 1.0f) * 512.0f;
-  t = fminf(fmaxf(t, 0.0f), 1023.0f);
+// u in [-U, U] to bpa bits (bpa <= 10)
+__device__ __forceinline__ uint32_t quant(float u, float inv_u, int bpa) {
+  float t = (u * inv_u + 1.0f) * (float)(1 << (bpa - 1));
+  t = fminf(fmaxf(t, 0.0f), (float)((1 << bpa) - 1));
   return (uint32_t)t;
 }
 
-__global__ __launch_bounds__(256) void key_kernel(SortArgs a) {
+__global__ __launch_bounds__(256) void key_kernel(SortArgs a, int key_shift) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_total) return;
   const int b = a.bid[i];
@@ -88,10 +96,11 @@ __global__ __launch_bounds__(256) void key_kernel(SortArgs a) {
   const BunchDev& B = a.bunches[b];
   const float U = __uint_as_float(a.ubits[b]);
   const float inv_u = U > 0.f ? 1.0f / U : 0.f;
-  const uint32_t m = spread3(quant10(a.xh[i], inv_u)) | (spread3(quant10(a.yh[i], inv_u)) << 1) |
-                     (spread3(quant10(a.zh[i], inv_u)) << 2);
+  const int bpa = morton_bits_for(B.n);  // the bunch's own resolution: same order alone or in a batch
+  const uint32_t m = spread3(quant(a.xh[i], inv_u, bpa)) | (spread3(quant(a.yh[i], inv_u, bpa)) << 1) |
+                     (spread3(quant(a.zh[i], inv_u, bpa)) << 2);
   const int64_t c = B.cstart + (i - B.off);
-  a.keys[c] = ((uint64_t)(uint32_t)b << 30) | m;
+  a.keys[c] = ((uint64_t)(uint32_t)b << key_shift) | m;
   a.vals[c] = (int32_t)i;
 }
 
@@ -279,9 +288,15 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 }  // namespace
 
 hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, hipStream_t s) {
+  return launch_sort_bits(a, 30, key_bits, n_groups_total, s);
+}
+
+hipError_t launch_sort_bits(const SortArgs& a, int key_shift, int key_bits, int32_t n_groups_total,
+                            hipStream_t s) {
+  if (key_shift < 3 || key_shift > 30 || key_bits < key_shift || key_bits > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bound_zero_kernel, dim3(nblk(a.nb, 256)), dim3(256), 0, s, a.ubits, a.nb);
   hipLaunchKernelGGL(bound_kernel, dim3(nblk(a.n_total, 256 * BOUND_PER)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a, key_shift);
   const int32_t n_tiles = (int32_t)nblk(a.n_in, TILE);
   uint64_t* kin = a.keys;
   int32_t* vin = a.vals;
