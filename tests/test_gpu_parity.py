@@ -255,7 +255,9 @@ def test_fp64_symmetric_batch_equals_separate_contexts_bitwise():
 
 
 def _batch_equals_separate(prec, tuning):
-    bunches = [wl.workload("gaussian_65536", n_override=n)[0] for n in (700, 1300, 2100)]
+    # sizes with different Morton resolutions (4, 5, 5 and 6 bits per axis): the
+    # far split's sort keys then differ in width alone and in the batch
+    bunches = [wl.workload("gaussian_65536", n_override=n)[0] for n in (70, 700, 1300, 5000)]
     say(f"batch == separate {prec} {tuning}")
     with Sim(bunches, prec, tuning=tuning) as sim:
         sim.push(3)
