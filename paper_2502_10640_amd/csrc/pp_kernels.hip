@@ -176,7 +176,7 @@ void pair_mixed_kernel(PairArgs a, int32_t sum_tile) {
 template <int K, bool UQ, bool PHI, bool DIAG>
 __device__ __forceinline__ void acc_fp64(const double4* __restrict__ sj, int jb, int je, int jbase,
                                          const int (&li)[K], const double (&xi)[K], const double (&yi)[K],
-                                         const double (&zi)[K], double eps2, double (&tx)[K],
+                                         const double (&zi)[K], double eps2, const SeriesConst& sc, double (&tx)[K],
                                          double (&ty)[K], double (&tz)[K], double (&tp)[K]) {
 #pragma unroll 2
   for (int jj = jb; jj < je; ++jj) {
@@ -193,7 +193,7 @@ __device__ __forceinline__ void acc_fp64(const double4* __restrict__ sj, int jb,
         if (self) r2 = 1.0;
       }
       double inv = 0.0;
-      const double s3 = inv_r3_64<PHI>(r2, inv);
+      const double s3 = inv_r3_64<PHI>(r2, sc, inv);
       double s = UQ ? s3 : p.w * s3;
       double ph = UQ ? inv : p.w * inv;
       if (DIAG) {
@@ -229,6 +229,7 @@ __global__ __launch_bounds__(WG) void pair_fp64_kernel(PairArgs a, int32_t sum_t
     const int64_t off = B.off;
     const int n = (int)B.n;
     const double eps2 = B.eps2;
+    const SeriesConst sc = series_const();  // series constants held in registers
 
     int li[K];
     double xi[K], yi[K], zi[K];
@@ -265,9 +266,9 @@ __global__ __launch_bounds__(WG) void pair_fp64_kernel(PairArgs a, int32_t sum_t
 #pragma unroll
         for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = tp[k] = 0.0;
         if (diag)
-          acc_fp64<K, UQ, PHI, true>(s_j, s0, se, jt, li, xi, yi, zi, eps2, tx, ty, tz, tp);
+          acc_fp64<K, UQ, PHI, true>(s_j, s0, se, jt, li, xi, yi, zi, eps2, sc, tx, ty, tz, tp);
         else
-          acc_fp64<K, UQ, PHI, false>(s_j, s0, se, jt, li, xi, yi, zi, eps2, tx, ty, tz, tp);
+          acc_fp64<K, UQ, PHI, false>(s_j, s0, se, jt, li, xi, yi, zi, eps2, sc, tx, ty, tz, tp);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           two_sum(Sx[k], Cx[k], tx[k]);

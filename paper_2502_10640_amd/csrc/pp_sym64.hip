@@ -51,8 +51,8 @@ __device__ __forceinline__ void two_sum_pair64(double& s, double& c, double t, d
 template <int K, bool UQ, bool PHI, bool DIAG>
 __device__ __forceinline__ void sweep_group64(const double4* __restrict__ sj, int l, int gsel,
                                               const double (&xi)[K], const double (&yi)[K], const double (&zi)[K],
-                                              const double (&qi)[K], double eps2, double (&ti)[3][K],
-                                              double (&tip)[K], double (&aj)[4]) {
+                                              const double (&qi)[K], double eps2, const SeriesConst& sc,
+                                              double (&ti)[3][K], double (&tip)[K], double (&aj)[4]) {
   // aj: plain partial of the source met in step s, (l + s) mod 64, which moves
   // one lane down after every step; after the 64 steps lane l holds the whole
   // group's partial of its own source l (64 terms in a plain FP64 sum, as the
@@ -72,7 +72,7 @@ __device__ __forceinline__ void sweep_group64(const double4* __restrict__ sj, in
       // self term: receiver group gsel + k meets source lane l at step 0
       self[k] = DIAG && s == 0 && gsel == k;
       if (DIAG && self[k]) r2 = 1.0;
-      s3[k] = inv_r3_64<PHI>(r2, inv[k]);
+      s3[k] = inv_r3_64<PHI>(r2, sc, inv[k]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -116,6 +116,7 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
   constexpr int BS = SYM64_WAVES * 64 * K;
   const int ibase = it.I * BS, jbase0 = it.J * BS;
   const bool pad = (n - ibase < BS) || (n - jbase0 < BS);  // a ragged last block takes part
+  const SeriesConst sc = series_const();  // series constants held in registers
   const double eps2 = B.eps2;
   const int64_t rho = it.r - a.r0;
   double* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
@@ -162,9 +163,9 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     double aj[4] = {0.0, 0.0, 0.0, 0.0};
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
     if (UQ && PHI && pad)  // unit weights 1.0 for real particles give the same bits as the uniform path
-      sweep_group64<K, false, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
+      sweep_group64<K, false, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, sc, ti, tip, aj);
     else
-      sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, ti, tip, aj);
+      sweep_group64<K, UQ, PHI, DIAG>(sj, l, DIAG ? g - w * K : -1, xi, yi, zi, qi, eps2, sc, ti, tip, aj);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       two_sum(Si[0][k], Ci[0][k], ti[0][k]);
