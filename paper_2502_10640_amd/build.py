@@ -21,7 +21,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["pp_kernels.hip", "pp_sym.hip", "pp_sym64.hip", "pp_sort.hip", "pp_runtime.hip"]
 ARCH = "gfx950"
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]

@@ -459,6 +459,7 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
 __global__ __launch_bounds__(256) void fill_bid_kernel(int32_t* bid, int64_t n_total, const BunchDev* bunches,
                                                        int32_t n_bunches) {
   const int b = blockIdx.y;
+  if (b >= n_bunches) return;  // the grid's y extent is the bunch count
   const BunchDev& B = bunches[b];
   for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < B.n;
        li += (int64_t)gridDim.x * blockDim.x) {

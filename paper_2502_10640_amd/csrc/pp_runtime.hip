@@ -144,6 +144,18 @@ pp_status dev_fail(pp_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return dev_fail((c), e_, #call); \
   } while (0)
 
+// Frees a context-owned device buffer before it is reallocated (callers have
+// synchronised the stream, so nothing of it is in flight); a failure is a
+// device error of the context.
+template <typename T>
+pp_status release(pp_ctx* c, T*& p) {
+  if (!p) return PP_OK;
+  void* q = p;
+  p = nullptr;
+  PP_HIP(c, hipFree(q));
+  return PP_OK;
+}
+
 pp_status usable(pp_ctx* c) {
   if (!c) return set_err(nullptr, PP_ERR_INVALID_ARG, "null context");
   if (c->broken) return set_err(c, PP_ERR_STATE, "context is broken by an earlier device failure: " + c->err);
@@ -164,8 +176,12 @@ hipError_t dalloc(T** p, size_t count) {
 // no asynchronous copy ever touches pageable memory.
 pp_status ensure_pin(pp_ctx* c, size_t bytes) {
   if (bytes <= c->hpin_bytes) return PP_OK;
-  if (c->hpin) hipHostFree(c->hpin);
-  c->hpin = nullptr;
+  if (c->hpin) {
+    void* q = c->hpin;
+    c->hpin = nullptr;
+    c->hpin_bytes = 0;
+    PP_HIP(c, hipHostFree(q));
+  }
   c->hpin_bytes = 0;
   size_t want = std::max<size_t>(bytes, 1 << 16);
   PP_HIP(c, hipHostMalloc(&c->hpin, want, hipHostMallocDefault));
@@ -215,6 +231,7 @@ void set_sort_bits(pp_ctx* c) {
 }
 
 pp_status build_sym(pp_ctx* c) {
+  pp_status st;
   set_sort_bits(c);
   const int64_t BS = c->sym_block();
   std::vector<ppk::SymItem> items;
@@ -262,16 +279,14 @@ pp_status build_sym(pp_ctx* c) {
   }
   const size_t slot_need = (size_t)band * per_round;
   if (slot_need > c->slot_bytes) {
-    if (c->slot) hipFree(c->slot);
-    c->slot = nullptr;
     c->slot_bytes = 0;
+    if ((st = release(c, c->slot)) != PP_OK) return st;
     PP_HIP(c, hipMalloc(&c->slot, slot_need));
     c->slot_bytes = slot_need;
   }
   if (items.size() > c->sitems_cap) {
-    if (c->sitems) hipFree(c->sitems);
-    c->sitems = nullptr;
     c->sitems_cap = 0;
+    if ((st = release(c, c->sitems)) != PP_OK) return st;
     PP_HIP(c, dalloc(&c->sitems, items.size()));
     c->sitems_cap = items.size();
   }
@@ -306,6 +321,7 @@ pp_status build_sym(pp_ctx* c) {
 constexpr int64_t kFillChunks = 32;
 
 pp_status build_items(pp_ctx* c) {
+  pp_status st;
   // kernels still in flight may read the old list and partial planes
   PP_HIP(c, hipStreamSynchronize(c->stream));
   const int K = c->k_eff();
@@ -391,17 +407,15 @@ pp_status build_items(pp_ctx* c) {
   const size_t esz = c->mixed() ? sizeof(float) : sizeof(double);
   const size_t need = (size_t)ppk::N_PLANES * (size_t)std::max<int64_t>(pbase, 1) * esz;
   if (need > c->part_bytes) {
-    if (c->part) hipFree(c->part);
-    c->part = nullptr;
     c->part_bytes = 0;
+    if ((st = release(c, c->part)) != PP_OK) return st;
     PP_HIP(c, hipMalloc(&c->part, need));
     c->part_bytes = need;
   }
   c->P = pbase;
   if (items.size() > c->items_cap) {
-    if (c->items) hipFree(c->items);
-    c->items = nullptr;
     c->items_cap = 0;
+    if ((st = release(c, c->items)) != PP_OK) return st;
     PP_HIP(c, dalloc(&c->items, items.size()));
     c->items_cap = items.size();
   }
@@ -643,8 +657,11 @@ pp_status enqueue_steps(pp_ctx* c, int64_t n, hipStream_t s, bool timed) {
   return PP_OK;
 }
 
+// Teardown of handles the context no longer uses: a failure here leaves
+// nothing to recover, so the results of these destroy/free calls are dropped
+// on purpose ((void) casts).
 void drop_graph(pp_ctx* c) {
-  if (c->graph.exec) hipGraphExecDestroy(c->graph.exec);
+  if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   c->graph = Graph{};
 }
 
@@ -656,13 +673,13 @@ pp_status capture_graph(pp_ctx* c, int64_t steps) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (st != PP_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return st;
   }
   if (e != hipSuccess) return dev_fail(c, e, "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate");
   c->graph.exec = ex;
   c->graph.steps = steps;
@@ -932,14 +949,14 @@ pp_status autotune(pp_ctx* c) {
 
 void free_all(pp_ctx* c) {
   drop_graph(c);
-  auto f = [](void* p) { if (p) hipFree(p); };
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
   f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
   f(c->items); f(c->sitems); f(c->acc); f(c->slot);
   f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
-  if (c->hpin) hipHostFree(c->hpin);
-  for (auto& e : c->ev_pool) hipEventDestroy(e);
-  for (auto& p : c->ev_used) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
-  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& p : c->ev_used) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
 }
 
 }  // namespace
@@ -1054,11 +1071,12 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
   hipError_t e = ppk::launch_minmax(c->dbunch, n_bunches, S.x, S.y, S.z, S.q, S.m, mm, G, c->stream);
   std::vector<double> ext((size_t)n_bunches * MM);
   if (e != hipSuccess) {
-    hipFree(mm);
+    (void)hipFree(mm);  // the set-up already failed
     return fail(dev_fail(c, e, "set-up reduction"));
   }
-  st0 = d2h(c, ext.data(), mm, ext.size() * sizeof(double));
-  hipFree(mm);
+  st0 = d2h(c, ext.data(), mm, ext.size() * sizeof(double));  // waits for the reduction
+  if (st0 == PP_OK) st0 = release(c, mm);
+  else (void)hipFree(mm);
   if (st0 != PP_OK) return fail(st0);
 
   bool uniform = true;
@@ -1167,9 +1185,8 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
   if (!c->phi) PP_HIP(c, dalloc(&c->phi, (size_t)c->n_total));
   const size_t need = (size_t)c->nb * ((size_t)G * ppk::D_N1 + ppk::D_NREC + ppk::D_OUT);
   if (need > c->diag_doubles) {
-    if (c->diag_buf) hipFree(c->diag_buf);
-    c->diag_buf = nullptr;
     c->diag_doubles = 0;
+    if ((s = release(c, c->diag_buf)) != PP_OK) return s;  // the last diagnostics call synchronised
     PP_HIP(c, dalloc(&c->diag_buf, need));
     c->diag_doubles = need;
   }
@@ -1271,7 +1288,7 @@ pp_status pp_sync(pp_ctx* c) {
 
 pp_status pp_destroy(pp_ctx* c) {
   if (!c) return PP_OK;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);  // teardown: nothing to report to
   free_all(c);
   delete c;
   return PP_OK;
