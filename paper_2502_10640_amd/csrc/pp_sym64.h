@@ -31,7 +31,7 @@ struct SymFoldArgs64 {
 
 // Wavefronts per item; a block is SYM64_WG * i_per_lane particles.  Four
 // wavefronts, not the mixed kernel's eight: the 4-receiver FP64 sweep needs
-// 160 VGPRs, so a CU holds 3 wavefronts per SIMD, which only 4-wavefront items
+// 164 VGPRs, so a CU holds 3 wavefronts per SIMD, which only 4-wavefront items
 // can fill (8-wavefront items leave it at 2 and measured 5% slower at 1M).
 constexpr int SYM64_WAVES = 4;
 constexpr int SYM64_WG = SYM64_WAVES * 64;
