@@ -545,6 +545,25 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     assert len(cache.read_text().splitlines()) == 3  # found in the cache: no second search
 
 
+def test_autotune_fp64_searches_both_schedules(orc, tmp_path, monkeypatch):
+    """On the FP64 path the search covers the ordered kernel and the FP64
+    symmetric schedule (1, 2 or 4 receivers per lane, never the far split);
+    whatever it keeps reproduces the field within the FP64 tolerance."""
+    b = wl.workload("gaussian_65536", n_override=24000)[0]
+    monkeypatch.setenv("PP_TUNE_CACHE", str(tmp_path / "tune64.txt"))
+    say(f"autotune fp64 n={b.n}")
+    with Sim([b], "fp64") as sim:
+        sim.step_batched(1, graph=False, autotune=True)
+        tuned = sim.tuning()
+        got = gpu_field(sim)
+        st = {k: sim.host(k) for k in ("x", "y", "z")}
+    print(f"    tuning chosen: {tuned}", flush=True)
+    assert tuned["far_split"] == 0 and tuned["i_per_lane"] in (1, 2, 4)
+    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
+    check_field(got, ref, TOL["fp64"], "autotuned fp64 tiling")
+    assert len((tmp_path / "tune64.txt").read_text().splitlines()) == 1
+
+
 # ---------------------------------------------------------------------------
 # the other benchmark workloads at full size, default tilings (as bench.py runs them)
 # ---------------------------------------------------------------------------
