@@ -247,6 +247,10 @@ def paper(a):
 
 def main():
     a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
     if a.mode == "drift":
         drift(a)
         return
@@ -256,10 +260,6 @@ def main():
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)
         return
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the multi-GPU path is not built",
-              file=sys.stderr)
-        sys.exit(2)
     import torch
     from paper_2502_10640_amd import pp
     from paper_2502_10640_amd import workloads as wl
