@@ -11,12 +11,14 @@
 // of a group, lane l meets source (l + s) mod 64 (every lane reads a distinct
 // LDS address; the group is stored twice so that the address needs no wrap).  The source-side partial of that source travels with it: after
 // each step every lane takes over the partial of its upper neighbour
-// (ds_bpermute, an explicit cross-lane move).  Every 16 steps the partials are
-// handed to their sources' home lanes (lane l owns source l) and added there
-// with two-sum.  After the group the 8 waves' pairs are combined in wave order
-// and stored as the source-side partial (S, C) of the item.  The receiver side
-// is a plain FP32 sum over each group of 64 sources, two-summed into
-// registers, and stored as the receiver-side partial at the end of the item.
+// (ds_bpermute, an explicit cross-lane move), so after the group's 64 steps
+// each partial is back at its source's home lane (lane l owns source l): a
+// plain FP32 sum of the wave's 64 K terms for that source.  The 8 waves'
+// partials are then added in wave order with two-sum and stored as the
+// source-side partial (S, C) of the item.  The receiver side is a plain FP32
+// sum over each group of 64 sources, two-summed into registers, and stored as
+// the receiver-side partial at the end of the item.  Both sides' plain sums
+// thus have the same worst-case bound, 63 u of their terms' magnitudes.
 //
 // Diagonal items (I == J, round 0) evaluate the ordered pairs inside one block
 // with the self term masked and have a receiver-side partial only.  Every
@@ -37,10 +39,10 @@ namespace {
 // zeros in both directions.
 constexpr float SENTINEL = 1.5e19f;
 
-// Steps of a source group unrolled per loop iteration (a divisor of the
-// 16-step hand-off period).  Measured on gfx950: 16 is fastest for 2 and 4
-// receivers per lane; with 1 per lane a 16-step body needs 129 VGPRs and 4
-// steps (75 VGPRs) is 14-24% faster.
+// Steps of a source group unrolled per loop iteration (a divisor of 64).
+// Measured on gfx950: 16 is fastest for 2 and 4 receivers per lane; with 1
+// per lane a 16-step body needs 129 VGPRs and 4 steps (75 VGPRs) is 14-24%
+// faster.
 template <int K>
 constexpr int sweep_unroll() { return K == 1 ? 4 : 16; }
 
@@ -54,15 +56,14 @@ __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, cons
                                             int gsel, const float (&xh)[K], const float (&yh)[K],
                                             const float (&zh)[K], const float (&xl)[K], const float (&yl)[K],
                                             const float (&zl)[K], const float (&qi)[K], float eps2,
-                                            float (&ti)[3][K], float (&tip)[K], float (&Sj)[4], float (&Cj)[4]) {
+                                            float (&ti)[3][K], float (&tip)[K], float (&aj)[4]) {
   // aj: plain partial of the source met in this step, (l + s) mod 64; it moves
   // one lane down every step so that it stays with its source.  The source
   // group is stored twice in LDS (entries 64..127 repeat 0..63), so step s
   // reads entry l + s with no wrap, at an immediate offset from the base of
-  // its block of 16 steps.
+  // its block of UNR steps.
   constexpr int UNR = sweep_unroll<K>();
-  static_assert(16 % UNR == 0, "the hand-off period is a whole number of iterations");
-  float aj[4] = {0.f, 0.f, 0.f, 0.f};
+  static_assert(64 % UNR == 0, "a group is a whole number of iterations");
   for (int s0 = 0; s0 < 64; s0 += UNR) {
     const float4* hb = sjh + (l + s0);
     const float4* lb = sjl + (l + s0);
@@ -115,21 +116,9 @@ __device__ __forceinline__ void sweep_group(const float4* __restrict__ sjh, cons
         }
       }
       if (!DIAG) {
-        if ((s & 15) == 15) {
-          // hand each partial to its source's home lane: lane l receives the
-          // partial of source l from lane (l - s) mod 64, adds it with two-sum
-          const int from = (l - s) & 63;
+        // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
 #pragma unroll
-          for (int q = 0; q < (PHI ? 4 : 3); ++q) {
-            const float m = lane_read(aj[q], from);
-            two_sum(Sj[q], Cj[q], m);
-            aj[q] = 0.f;
-          }
-        } else {
-          // lane l takes over the partial of source (l + s + 1) mod 64 from lane l + 1
-#pragma unroll
-          for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read(aj[q], (l + 1) & 63);
-        }
+        for (int q = 0; q < (PHI ? 4 : 3); ++q) aj[q] = lane_read(aj[q], (l + 1) & 63);
       }
     }
   }
@@ -236,7 +225,7 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     float ti[3][K], tip[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { ti[0][k] = ti[1][k] = ti[2][k] = tip[k] = 0.f; }
-    float Sj[4] = {0.f, 0.f, 0.f, 0.f}, Cj[4] = {0.f, 0.f, 0.f, 0.f};
+    float aj[4] = {0.f, 0.f, 0.f, 0.f};
     bool far = false;
     if (split) {
       if (jg >= n || ib[0] > ib[3]) {
@@ -257,10 +246,10 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     }
     // in a diagonal item the receivers of wave w, slot k belong to group w*K + k
     if (far)
-      sweep_group<K, UQ, PHI, DIAG, true>(sjh, sjl, l, -1, xh, yh, zh, xl, yl, zl, qi, eps2, ti, tip, Sj, Cj);
+      sweep_group<K, UQ, PHI, DIAG, true>(sjh, sjl, l, -1, xh, yh, zh, xl, yl, zl, qi, eps2, ti, tip, aj);
     else
       sweep_group<K, UQ, PHI, DIAG, false>(sjh, sjl, l, DIAG ? g - w * K : -1, xh, yh, zh, xl, yl, zl, qi, eps2,
-                                           ti, tip, Sj, Cj);
+                                           ti, tip, aj);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       two_sum(Si[0][k], Ci[0][k], ti[0][k]);
@@ -270,17 +259,14 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     }
     if (!DIAG) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xw[w][q][l] = Sj[q];
-        xw[w][4 + q][l] = Cj[q];
-      }
+      for (int q = 0; q < (PHI ? 4 : 3); ++q) xw[w][q][l] = aj[q];
       __syncthreads();
       // one thread per (source, component): waves 0-3 combine the 8 waves'
       // pairs in wave order and store the source-side partial
       const int q = tid >> 6;  // 0..2 field components, 3 potential
       if (q < (PHI ? 4 : 3)) {
-        float S = xw[0][q][l], C = xw[0][4 + q][l];
-        for (int ww = 1; ww < SYM_WAVES; ++ww) two_sum_pair(S, C, xw[ww][q][l], xw[ww][4 + q][l]);
+        float S = xw[0][q][l], C = 0.f;
+        for (int ww = 1; ww < SYM_WAVES; ++ww) two_sum(S, C, xw[ww][q][l]);
         if (jg + l < n) {
           const int o = g * 64 + l;
           sslot[(q < 3 ? q : 6) * BS + o] = S;
