@@ -14,7 +14,7 @@ one weight), expanding in vacuum from a given spatial and velocity
 distribution.  The paper's own bunch is a cubic lattice (Sec. 2.1 setup
 paragraph); the benchmark workloads are seeded spheres and Gaussians.
 
-Readings of points the paper does not fix (each one is listed in the design doc):
+Readings of points the paper does not fix:
   * mean spacing = (V / N_p)^(1/3), with V = 4 pi R^3 / 3 for a sphere and
     V = (2 pi)^(3/2) sx sy sz for a Gaussian (peak-density volume);
   * plasma frequency omega_p = sqrt(n_e e^2 / (eps0 m_e)), n_e = electrons / V;
