@@ -41,7 +41,15 @@ thread_local std::string g_create_error;
 struct Graph {
   hipGraphExec_t exec = nullptr;
   int64_t steps = 0;
+  int64_t phase = 0;        // step index modulo kResortEvery at capture
+  int64_t perm_offset = 0;  // step of the last sort inside the graph, relative to its first step - 1
 };
+
+// The far split's Morton order is recomputed at evaluations whose step index is
+// a multiple of kResortEvery and reused in between (the bound, the sorted
+// mirror, the rank and the group boxes are still computed every evaluation
+// from the current positions, so the far test is always exact).
+constexpr int64_t kResortEvery = 8;
 
 }  // namespace
 
@@ -118,6 +126,7 @@ struct pp_ctx {
   bool far() const { return mixed() && sym() && tun.far_split > 0; }
   size_t acc_elem() const { return mixed() ? sizeof(float) : sizeof(double); }
   int key_shift = 30, key_bits = 30;  // sort key layout of the far split (set_sort_bits)
+  int64_t perm_k = -1;  // step index of the evaluation whose positions the current order sorts (-1: none)
   int k_eff() const { return mixed() ? tun.i_per_lane : std::min(tun.i_per_lane, 4); }
   // particles per block of the symmetric schedule
   int64_t sym_block() const { return (int64_t)(mixed() ? ppk::SYM_WG : ppk::SYM64_WG) * tun.i_per_lane; }
@@ -527,7 +536,21 @@ pp_status mark(pp_ctx* c, bool timed, bool begin, hipStream_t s) {
   return PP_OK;
 }
 
-pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
+// Reuse the current order at an evaluation of step k when it sorts the
+// positions of the last multiple of kResortEvery up to k (or of k itself):
+// a function of k and of the evaluations before it, so eager steps, graph
+// replays, split runs and repeated evaluations of one step all agree.
+bool perm_reusable(const pp_ctx* c, int64_t k) {
+  return c->perm_k >= 0 && (c->perm_k == k || (k % kResortEvery != 0 && c->perm_k == k - k % kResortEvery));
+}
+
+// the order is aligned at the current step: the next evaluations follow the
+// every-kResortEvery rule (what a captured graph assumes)
+bool perm_aligned(const pp_ctx* c) {
+  return !c->far() || c->perm_k == c->step - c->step % kResortEvery;
+}
+
+pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k) {
   pp_status st;
   if (timed) ++c->prof_evals;
   if (c->sym() && !c->mixed()) {
@@ -589,7 +612,9 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed) {
       }
       so.rank = c->rank;
       so.gbox = c->gbox;
-      PP_HIP(c, ppk::launch_sort_bits(so, c->key_shift, c->key_bits, c->n_groups, s));
+      const bool resort = !perm_reusable(c, k);
+      if (resort) c->perm_k = k;
+      PP_HIP(c, ppk::launch_sort_bits(so, c->key_shift, c->key_bits, c->n_groups, resort, s));
       sa.xh = sp[0]; sa.yh = sp[1]; sa.zh = sp[2];
       sa.xl = sp[3]; sa.yl = sp[4]; sa.zl = sp[5];
       sa.qt = sp[6];
@@ -635,22 +660,22 @@ pp_status ensure_accel(pp_ctx* c) {
   if (c->a_valid) return PP_OK;
   pp_status s;
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, false, c->stream, c->prof)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, false, c->stream, c->prof, c->step)) != PP_OK) return s;
   if ((s = enqueue_final(c, ppk::FIN_ACCEL, nullptr, nullptr, nullptr, nullptr, c->stream)) != PP_OK) return s;
   c->a_valid = true;
   return PP_OK;
 }
 
-// n >= 1 Velocity Verlet steps on stream s: the first drift, then per step the
-// pair stage and the kick; the kick of every step but the last also does the
-// next step's drift and mirror pack (2n + 1 kernels of the ordered path instead
-// of 3n, with the same arithmetic).
+// n >= 1 Velocity Verlet steps on stream s from step c->step: the first drift,
+// then per step the pair stage and the kick; the kick of every step but the
+// last also does the next step's drift and mirror pack (2n + 1 kernels of the
+// ordered path instead of 3n, with the same arithmetic).
 pp_status enqueue_steps(pp_ctx* c, int64_t n, hipStream_t s, bool timed) {
   pp_status r;
   if (n <= 0) return PP_OK;
   if ((r = enqueue_pack(c, true, s)) != PP_OK) return r;
   for (int64_t k = 0; k < n; ++k) {
-    if ((r = enqueue_pair(c, false, s, timed)) != PP_OK) return r;
+    if ((r = enqueue_pair(c, false, s, timed, c->step + k + 1)) != PP_OK) return r;
     const ppk::FinalMode m = k + 1 < n ? ppk::FIN_KICK_DRIFT : ppk::FIN_KICK;
     if ((r = enqueue_final(c, m, nullptr, nullptr, nullptr, nullptr, s)) != PP_OK) return r;
   }
@@ -669,7 +694,13 @@ pp_status capture_graph(pp_ctx* c, int64_t steps) {
   drop_graph(c);
   PP_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
   pp_status st = PP_OK;
+  // the captured steps' sort decisions update the host's record of the order
+  // as if they had run; nothing has run yet, so it is restored afterwards and
+  // advanced at each replay instead
+  const int64_t perm_before = c->perm_k;
   st = enqueue_steps(c, steps, c->cap, false);
+  const int64_t perm_after = c->perm_k;
+  c->perm_k = perm_before;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (st != PP_OK) {
@@ -683,6 +714,8 @@ pp_status capture_graph(pp_ctx* c, int64_t steps) {
   if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate");
   c->graph.exec = ex;
   c->graph.steps = steps;
+  c->graph.phase = c->step % kResortEvery;
+  c->graph.perm_offset = perm_after - c->step;
   return PP_OK;
 }
 
@@ -770,6 +803,7 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
 
 pp_status apply_tuning(pp_ctx* c, const pp_tuning& t) {
   c->tun = t;
+  c->perm_k = -1;
   drop_graph(c);
   return build_items(c);
 }
@@ -846,7 +880,7 @@ pp_status time_eval(pp_ctx* c, int reps, double* ms) {
   for (int r = 0; r < reps && st == PP_OK; ++r) {
     if ((st = enqueue_pack(c, false, c->stream)) != PP_OK) break;
     PP_HIP(c, hipEventRecord(e0, c->stream));
-    if ((st = enqueue_pair(c, false, c->stream, false)) != PP_OK) break;
+    if ((st = enqueue_pair(c, false, c->stream, false, c->step)) != PP_OK) break;
     PP_HIP(c, hipEventRecord(e1, c->stream));
     PP_HIP(c, hipEventSynchronize(e1));
     float f = 0.f;
@@ -862,7 +896,7 @@ pp_status time_eval(pp_ctx* c, int reps, double* ms) {
 pp_status field_into(pp_ctx* c, double* ex, double* ey, double* ez) {
   pp_status s;
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, false, c->stream, false)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, false, c->stream, false, c->step)) != PP_OK) return s;
   return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, nullptr, c->stream);
 }
 
@@ -1137,7 +1171,7 @@ pp_status pp_field(pp_ctx* c, double* ex, double* ey, double* ez, double* phi) {
   if ((s = usable(c)) != PP_OK) return s;
   if (!ex || !ey || !ez) return set_err(c, PP_ERR_INVALID_ARG, "field outputs must not be NULL");
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, phi != nullptr, c->stream, false)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, phi != nullptr, c->stream, false, c->step)) != PP_OK) return s;
   return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, phi, c->stream);
 }
 
@@ -1162,11 +1196,21 @@ pp_status pp_step_batched(pp_ctx* c, int64_t n_steps, uint32_t flags) {
   if ((s = ensure_accel(c)) != PP_OK) return s;
   int64_t left = n_steps;
   if ((flags & PP_GRAPH) && left >= c->tun.graph_steps) {
-    if (!c->graph.exec || c->graph.steps != c->tun.graph_steps) {
-      if ((s = capture_graph(c, c->tun.graph_steps)) != PP_OK) return s;
+    // a graph's sort decisions assume the order aligned to the every-
+    // kResortEvery rule: after an invalidation, step eagerly until it is
+    while (left > 0 && !perm_aligned(c)) {
+      if ((s = enqueue_steps(c, 1, c->stream, c->prof)) != PP_OK) return s;
+      c->step += 1;
+      --left;
     }
-    while (left >= c->graph.steps) {
+    while (left >= c->tun.graph_steps) {
+      // one graph per step phase (its baked sort decisions depend on it)
+      if (!c->graph.exec || c->graph.steps != c->tun.graph_steps ||
+          (c->far() && c->graph.phase != c->step % kResortEvery)) {
+        if ((s = capture_graph(c, c->tun.graph_steps)) != PP_OK) return s;
+      }
       PP_HIP(c, hipGraphLaunch(c->graph.exec, c->stream));
+      if (c->far()) c->perm_k = c->step + c->graph.perm_offset;
       left -= c->graph.steps;
       c->step += c->graph.steps;
     }
@@ -1191,7 +1235,7 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
     c->diag_doubles = need;
   }
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, true, c->stream, false)) != PP_OK) return s;
+  if ((s = enqueue_pair(c, true, c->stream, false, c->step)) != PP_OK) return s;
   if ((s = enqueue_final(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, c->phi, c->stream)) != PP_OK) return s;
   ppk::DiagArgs d{};
   d.bunches = c->dbunch;
@@ -1224,6 +1268,7 @@ pp_status pp_invalidate(pp_ctx* c) {
   pp_status s;
   if ((s = usable(c)) != PP_OK) return s;
   c->a_valid = false;
+  c->perm_k = -1;
   return PP_OK;
 }
 

@@ -18,7 +18,10 @@ __host__ __device__ inline int morton_bits_for(int64_t n) {
 // bunch's code has 3 morton_bits_for(n) bits and key_shift (3..30) is the
 // widest of them; key_bits = key_shift plus the bits of the largest bunch
 // index, sorted in ceil(key_bits / 8) radix passes.
-hipError_t launch_sort_bits(const SortArgs& a, int key_shift, int key_bits, int32_t n_groups_total,
+// With resort false the permutation of the previous full sort (same key_bits)
+// is reused: only the bound, the gather into the sorted mirror, the rank and
+// the group boxes are recomputed from the current positions.
+hipError_t launch_sort_bits(const SortArgs& a, int key_shift, int key_bits, int32_t n_groups_total, bool resort,
                             hipStream_t s);
 
 }  // namespace ppk

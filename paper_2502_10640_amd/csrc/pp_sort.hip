@@ -288,22 +288,27 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 }  // namespace
 
 hipError_t launch_sort(const SortArgs& a, int key_bits, int32_t n_groups_total, hipStream_t s) {
-  return launch_sort_bits(a, 30, key_bits, n_groups_total, s);
+  return launch_sort_bits(a, 30, key_bits, n_groups_total, true, s);
 }
 
-hipError_t launch_sort_bits(const SortArgs& a, int key_shift, int key_bits, int32_t n_groups_total,
+hipError_t launch_sort_bits(const SortArgs& a, int key_shift, int key_bits, int32_t n_groups_total, bool resort,
                             hipStream_t s) {
   if (key_shift < 3 || key_shift > 30 || key_bits < key_shift || key_bits > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bound_zero_kernel, dim3(nblk(a.nb, 256)), dim3(256), 0, s, a.ubits, a.nb);
   hipLaunchKernelGGL(bound_kernel, dim3(nblk(a.n_total, 256 * BOUND_PER)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a, key_shift);
   const int32_t n_tiles = (int32_t)nblk(a.n_in, TILE);
   uint64_t* kin = a.keys;
   int32_t* vin = a.vals;
   uint64_t* kout = a.keys2;
   int32_t* vout = a.vals2;
   const int passes = (key_bits + 7) / 8;
-  for (int p = 0; p < passes; ++p) {
+  if (!resort) {
+    // the previous sort left its permutation in the buffer of its last pass
+    if (passes % 2 == 1) vin = a.vals2;
+  } else {
+    hipLaunchKernelGGL(key_kernel, dim3(nblk(a.n_total, 256)), dim3(256), 0, s, a, key_shift);
+  }
+  for (int p = 0; resort && p < passes; ++p) {
     const int shift = 8 * p;
     hipLaunchKernelGGL(hist_kernel, dim3(n_tiles), dim3(RT), 0, s, kin, a.n_in, shift, a.hist, n_tiles);
     hipLaunchKernelGGL(digit_total_kernel, dim3(256), dim3(256), 0, s, a.hist, n_tiles, a.dtot);
