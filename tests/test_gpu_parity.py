@@ -630,6 +630,32 @@ def test_graph_replays_match_eager_steps_one_by_one(variant):
                 np.testing.assert_array_equal(g.host(k), e.host(k), err_msg=f"replay {rep} {k}")
 
 
+def test_far_split_order_reuse_matches_one_step_pushes():
+    """The far split's Morton order is recomputed at steps that are multiples
+    of 8 and reused in between.  Graph replays of 3 steps (every phase of the
+    rule), diagnostics and field evaluations between calls, and an
+    invalidation at a step that is not a multiple of 8 must give the bits of a
+    twin context advanced by one-step pushes with the same invalidation."""
+    tun = {"graph_steps": 3, "symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    b = wl.workload("gaussian_65536", n_override=6000)[0]
+    say("far split order reuse vs one-step pushes (graphs of 3, diagnostics, invalidation at step 5)")
+    with Sim([b], "mixed", tuning=tun) as g, Sim([b], "mixed", tuning=tun) as e:
+        g.step_batched(5, graph=True)
+        g.diagnostics()
+        g.field(want_phi=True)
+        for _ in range(5):
+            e.push(1)
+        g.invalidate()
+        e.invalidate()
+        g.step_batched(13, graph=True)  # eager to step 8, graphs from phases 0, 3, 6, then eager
+        g.diagnostics()
+        g.step_batched(7, graph=False)
+        for _ in range(20):
+            e.push(1)
+        for k in ("x", "y", "vx", "vz"):
+            np.testing.assert_array_equal(g.host(k), e.host(k), err_msg=k)
+
+
 def test_simulation_calls_under_another_current_stream(orc, gpu):
     """The wrapper runs every call on its context's stream: a caller whose
     current torch stream is another one still gets the right field (the output
