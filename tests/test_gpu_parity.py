@@ -656,6 +656,45 @@ def test_far_split_order_reuse_matches_one_step_pushes():
             np.testing.assert_array_equal(g.host(k), e.host(k), err_msg=k)
 
 
+@pytest.mark.parametrize("sched", ["ordered", "symmetric"])
+def test_fp64_two_body_closed_form_over_eleven_decades(sched):
+    """Independent of the oracle: 32 two-particle bunches with separations from
+    1e-9 m to 100 m along a skew direction, no softening.  Each particle's FP64
+    field must be k w q (r_i - r_j) / |r_i - r_j|^3 (Eq. (A)/(B) for one pair),
+    evaluated here in 40-digit decimal arithmetic from the same doubles, to
+    within 2e-15 relative: v_rsq_f64 alone is good to ~2^-24 and one Newton
+    step to ~4e-15, so either shortcut would fail."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    pi = Decimal("3.141592653589793238462643383279502884197")
+    k = 1 / (4 * pi * Decimal(repr(wl.EPS0)))
+    bunches, expect = [], []
+    for i in range(32):
+        d = 10.0 ** (-9 + 11 * i / 31)
+        x = np.array([0.0, d / 3]); y = np.array([0.0, 2 * d / 3]); z = np.array([0.0, -2 * d / 3])
+        q = np.full(2, -wl.E_CHARGE); m = np.full(2, wl.M_ELECTRON); zero = np.zeros(2)
+        w = 7.0
+        bunches.append(wl.Bunch(x, y, z, zero, zero.copy(), zero.copy(), q, m, w, 0.0, 1e-15, 0, {}))
+        dx, dy, dz = (Decimal(repr(float(a[0]))) - Decimal(repr(float(a[1]))) for a in (x, y, z))
+        r = (dx * dx + dy * dy + dz * dz).sqrt()
+        f = k * Decimal(repr(w)) * Decimal(repr(-wl.E_CHARGE)) / (r * r * r)
+        expect.append([float(f * dx), float(f * dy), float(f * dz)])  # on particle 0; particle 1 opposite
+    tun = None if sched == "ordered" else {"symmetric": 1, "i_per_lane": 1}
+    say(f"fp64 two-body closed form, 32 separations 1e-9..1e2 m ({sched})")
+    with Sim(bunches, "fp64", tuning=tun) as sim:
+        f = gpu_field(sim)
+        worst = 0.0
+        for i in range(len(bunches)):
+            sl = sim.bunch_slice(i)
+            g = np.stack([f["ex"][sl], f["ey"][sl], f["ez"][sl]], 1)
+            e = np.array(expect[i])
+            for row, sign in ((0, 1.0), (1, -1.0)):
+                rel = np.abs(g[row] - sign * e).max() / np.abs(e).max()
+                worst = max(worst, rel)
+                assert rel <= 2e-15, (i, row, g[row], sign * e, rel)
+    print(f"    worst relative error {worst:.3e}", flush=True)
+
+
 def test_simulation_calls_under_another_current_stream(orc, gpu):
     """The wrapper runs every call on its context's stream: a caller whose
     current torch stream is another one still gets the right field (the output
