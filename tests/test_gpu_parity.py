@@ -578,6 +578,23 @@ def test_full_size_parity_gaussian_65536(orc, prec):
     check_field(got, oracle_field(orc, b), TOL[prec], f"gaussian_65536/{prec}")
 
 
+def test_full_size_energy_drift_cold_sphere_1m_200_steps():
+    """The benchmark's 1 048 576-particle cold sphere in mixed precision with
+    its default tiling: over 200 Velocity Verlet steps (hipGraph replay) the
+    total energy (the library's own FP64 diagnostics) drifts by at most 1e-6
+    of its initial value."""
+    b = wl.workload("cold_sphere_1m")[0]
+    say(f"energy drift cold_sphere_1m mixed, 200 steps, n={b.n}")
+    with Sim([b], "mixed") as sim:
+        e0 = sim.diagnostics()[0]["total"]
+        sim.step_batched(200, graph=True)
+        d = sim.diagnostics()[0]
+    drift = abs(d["total"] - e0) / abs(e0)
+    print(f"    step {d['step']}: relative energy drift {drift:.3e}", flush=True)
+    assert d["step"] == 200
+    assert drift <= 1e-6
+
+
 def test_full_size_sampled_parity_ellipsoid_4m(orc):
     b = wl.workload("ellipsoid_4m")[0]
     rng = np.random.default_rng(98)
