@@ -394,11 +394,12 @@ def test_symmetric_field_parity(orc, prec, K):
             check_field(got, oracle_field(orc, b), TOL[prec], f"sym {prec} K={K} n={b.n}")
 
 
+@pytest.mark.parametrize("K", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
-def test_symmetric_push_graph_and_trajectory(orc, prec):
+def test_symmetric_push_graph_and_trajectory(orc, prec, K):
     b = wl.workload("gaussian_65536", n_override=2500)[0]
-    say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}")
-    tun = {"symmetric": 1, "i_per_lane": 1, "graph_steps": 3}
+    say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}, K={K}")
+    tun = {"symmetric": 1, "i_per_lane": K, "graph_steps": 3}
     res = []
     for mode in ("push", "graph"):
         with Sim([b], prec, tuning=tun) as sim:
