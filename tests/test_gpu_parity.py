@@ -718,6 +718,31 @@ def test_two_body_closed_form_over_eleven_decades(prec, sched):
     print(f"    worst relative error {worst:.3e}", flush=True)
 
 
+def test_time_field_and_profile_leave_the_run_unchanged():
+    """pp_time_field returns a positive time and the ordered pair count, and
+    neither it nor the event profiling changes a run's bits: 3 steps, a timed
+    field, 3 more steps with profiling on equal 6 plain steps (far split on,
+    so the order-reuse rule is exercised too)."""
+    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    b = wl.workload("gaussian_65536", n_override=5000)[0]
+    say("pp_time_field and profiling leave the trajectory unchanged")
+    with Sim([b], "mixed", tuning=tun) as t, Sim([b], "mixed", tuning=tun) as e:
+        t.push(3)
+        with t._on():
+            ms, pairs = pp.pp_time_field(t.ctx, 2)
+            pp.pp_set_profiling(t.ctx, True)
+        assert ms > 0.0 and pairs == float(b.n) * (b.n - 1)
+        t.push(3)
+        with t._on():
+            prof = pp.pp_get_profile(t.ctx)
+            pp.pp_set_profiling(t.ctx, False)
+        assert prof["evaluations"] == 3 and prof["launches"] >= 3 and prof["total_ms"] > 0.0
+        assert prof["pairs"] == pairs
+        e.push(6)
+        for k in ("x", "vx", "vz"):
+            np.testing.assert_array_equal(t.host(k), e.host(k), err_msg=k)
+
+
 def test_simulation_calls_under_another_current_stream(orc, gpu):
     """The wrapper runs every call on its context's stream: a caller whose
     current torch stream is another one still gets the right field (the output
