@@ -99,6 +99,33 @@ def test_field_parity(orc, prec, case):
 RAGGED = [1, 2, 3, 63, 255, 256, 257, 511, 513, 777, 1025, 2049]
 
 
+@pytest.mark.parametrize("sched", ["ordered", "symmetric_far"])
+def test_three_hundred_small_bunches(orc, sched):
+    """300 bunches of 1..100 particles in one context (nine bunch-index bits in
+    the far split's sort keys, a long bunch table): every bunch's field against
+    the oracle."""
+    rng = np.random.default_rng(404)
+    sizes = [int(v) for v in rng.integers(1, 101, 300)]
+    bunches = [wl.cold_sphere(n, 20e-6, 1e4 * n, 1e-3, 0.01, 0, seed=5000 + k, name=f"s{k}")
+               for k, n in enumerate(sizes)]
+    tun = None if sched == "ordered" else {"symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    say(f"300 small bunches ({sched}), {sum(sizes)} particles")
+    with Sim(bunches, "mixed", tuning=tun) as sim:
+        full = gpu_field(sim)
+        slices = [sim.bunch_slice(k) for k in range(len(bunches))]
+    worst = 0.0
+    for k, b in enumerate(bunches):
+        got = {key: v[slices[k]] for key, v in full.items()}
+        if b.n == 1:
+            assert got["ex"][0] == 0 and got["phi"][0] == 0
+            continue
+        ref = oracle_field(orc, b)
+        e = l2_rel(vec(got), vec(ref))
+        worst = max(worst, e)
+        assert e <= TOL["mixed"] and cond_max(vec(got), vec(ref), ref["amag"]) <= TOL["mixed"], (k, b.n, e)
+    print(f"    worst relative L2 over the bunches {worst:.3e}", flush=True)
+
+
 RAGGED_TUNINGS = {"ordered": None, "symmetric": {"symmetric": 1, "i_per_lane": 1, "far_split": 0},
                   "symmetric_k4": {"symmetric": 1, "i_per_lane": 4, "far_split": 0}}
 
