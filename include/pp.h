@@ -138,7 +138,9 @@ typedef struct {
                             the ordered-pair kernel                             */
   int32_t far_split;     /* PP_MIXED symmetric only: 0 keeps the hi/lo separations of
                             Sec. 3 for every pair; f in 1..4 orders each bunch
-                            along a Morton curve every evaluation and uses plain
+                            along a Morton curve (recomputed at steps that are
+                            multiples of 8, reused in between; the boxes below
+                            always come from the current positions) and uses plain
                             FP32 separations for a 64-source group whose box is
                             farther than D = 2^-f min(U, (|a| + |b|)/2) from
                             the box of a wavefront's receivers (U: largest
@@ -192,10 +194,12 @@ pp_status pp_step_batched(pp_ctx *ctx, int64_t n_steps, uint32_t flags);
 pp_status pp_diagnostics(pp_ctx *ctx, pp_diag *out);
 
 /* Declare that the caller changed r or v (the cached acceleration and the
- * step counter's meaning are reset: a(t) is recomputed on the next push). */
+ * step counter's meaning are reset: a(t) is recomputed on the next push; the
+ * far split's spatial order is recomputed at the next evaluation). */
 pp_status pp_invalidate(pp_ctx *ctx);
 
-/* Read or replace the tiling.  Setting checks ranges (PP_ERR_INVALID_ARG). */
+/* Read or replace the tiling.  Setting checks ranges (PP_ERR_INVALID_ARG) and
+ * drops captured graphs and the far split's spatial order. */
 pp_status pp_get_tuning(const pp_ctx *ctx, pp_tuning *out);
 pp_status pp_set_tuning(pp_ctx *ctx, const pp_tuning *tuning);
 
