@@ -60,10 +60,13 @@ def parse():
     p.add_argument("--tuning", default="", help="k=v,... tiling override (i_per_lane, sum_tile, ...)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
-    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper"],
+    p.add_argument("--cpu-threads", type=int, default=0,
+                   help="oracle threads for --mode oracle (0: every host core)")
+    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper", "oracle"],
                    help="drift: run --steps steps in mixed and FP64 precision and report the total-energy drift "
                         "and the mixed-vs-FP64 energy gap every --every steps (no timing line); paper: the "
-                        "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases)")
+                        "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases); "
+                        "oracle: time only the CPU oracle on --cpu-threads threads (no GPU)")
     p.add_argument("--paper-cases", default="main,dt,np", help="subset of main,dt,np for --mode paper")
     p.add_argument("--every", type=int, default=20)
     p.add_argument("--precisions", default="mixed,fp64")
@@ -86,12 +89,15 @@ def calibrate_copy(mib):
                       "copies": 3}))
 
 
-def cpu_baseline(bunches, target_s):
+def cpu_baseline(bunches, target_s, threads=0):
     """Time the CPU oracle's field evaluation on a bounded sample of receivers
-    of the first bunch (every source), scaled to pairs/s."""
+    of the first bunch (every source), scaled to pairs/s; on every host core
+    unless ``threads`` names a count."""
     import numpy as np
     from oracle.oracle import default
     orc = default()
+    if threads:
+        orc.set_num_threads(threads)
     b = bunches[0]
     rng = np.random.default_rng(7)
     nrecv = 256
@@ -107,6 +113,17 @@ def cpu_baseline(bunches, target_s):
     return {"value": pairs / dt, "unit": "pair interactions/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": f"{recv.size} receivers x {b.n} sources of {b.meta.get('name', 'bunch')}, one FP64 field "
                       f"evaluation with compensated sums ({pairs:.3e} pairs in {dt:.2f} s)"}
+
+
+def oracle_only(a):
+    """The CPU oracle alone on the workload's first bunch (no GPU is touched):
+    the host-side reference rate, serial with --cpu-threads 1."""
+    from paper_2502_10640_amd import workloads as wl
+    bunches = wl.workload(a.workload, n_override=a.n or None)
+    base = cpu_baseline(bunches, a.cpu_seconds, a.cpu_threads)
+    print(json.dumps({"metric": "pair interactions/s (CPU oracle)", "value": base["value"],
+                      "unit": base["unit"], "cpu_baseline": base,
+                      "config": {"workload": a.workload, "n": bunches[0].n}}))
 
 
 def total_energy(sim):
@@ -256,6 +273,9 @@ def main():
         return
     if a.mode == "paper":
         paper(a)
+        return
+    if a.mode == "oracle":
+        oracle_only(a)
         return
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)

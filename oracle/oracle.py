@@ -87,6 +87,8 @@ class Oracle:
         L.oracle_coulomb_k.restype = ctypes.c_double
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
 
     @staticmethod
     def _d(a: np.ndarray):
@@ -105,6 +107,12 @@ class Oracle:
 
     def num_threads(self) -> int:
         return self.lib.oracle_num_threads()
+
+    def set_num_threads(self, n: int) -> None:
+        """Thread count of later calls (n >= 1); results do not depend on it."""
+        if n < 1:
+            raise ValueError("thread count must be >= 1")
+        self.lib.oracle_set_num_threads(int(n))
 
     def field(self, x, y, z, q, w: float, eps: float, recv=None, want_phi=False,
               want_amag=False):

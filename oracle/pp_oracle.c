@@ -284,3 +284,14 @@ int oracle_num_threads(void) {
 #endif
   return nt;
 }
+
+/* Sets the thread count of later parallel regions (n >= 1); the results do
+ * not depend on it.  Without OpenMP the oracle is serial and this does
+ * nothing. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

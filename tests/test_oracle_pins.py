@@ -384,3 +384,24 @@ def test_thread_count_independent(orc):
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
                                    text=True, check=True).stdout)
     assert outs[0] == outs[1] and len(outs[0]) > 100
+
+
+def test_set_num_threads_keeps_bits(orc):
+    """The in-process thread setter (used for the serial CPU rate) changes the
+    thread count, not the results."""
+    before = orc.num_threads()
+    rng = np.random.default_rng(2)
+    p = rng.normal(size=(3, 700))
+    q = rng.choice([-1.0, 1.0], size=700)
+    try:
+        outs = []
+        for nt in (1, 5):
+            orc.set_num_threads(nt)
+            assert orc.num_threads() == nt
+            f = orc.field(p[0], p[1], p[2], q, 1.0, 0.05, want_phi=True)
+            outs.append(b"".join(f[k].tobytes() for k in ("ex", "ey", "ez", "phi")))
+        assert outs[0] == outs[1]
+        with pytest.raises(ValueError):
+            orc.set_num_threads(0)
+    finally:
+        orc.set_num_threads(before)
