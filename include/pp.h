@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 2
+#define PP_ABI_VERSION 3
 
 typedef struct pp_ctx pp_ctx; /* opaque; owns its device scratch */
 
@@ -149,6 +149,13 @@ typedef struct {
                             Each such term then differs from the hi/lo term by
                             at most 2 sqrt(3) 2^-23 2^f relative (6.6e-6 at
                             f = 4, inside the mixed tolerance).                 */
+  int32_t sym_split;     /* symmetric only: 1, 2 or 4 items per block pair, each
+                            sweeping that fraction of the source block's
+                            64-source groups (diagonal blocks too), so that a
+                            bunch of a few block pairs per compute unit still
+                            fills the last wave of items.  Changes the order of
+                            additions, hence the bits.  The ordered schedule
+                            ignores it.                                         */
 } pp_tuning;
 
 /* Create a context over n_bunches bunches of a state of n_total particles.

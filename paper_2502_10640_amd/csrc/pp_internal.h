@@ -95,19 +95,23 @@ struct SymItem {
   int32_t b;
   int32_t I;
   int32_t J;
-  int32_t r;  // round; 0 = diagonal item
+  // sub-round r * split + h: round r of block pairs (0 = diagonal) and the
+  // part h < split of source block J's 64-source groups that the item sweeps
+  int32_t r;
 };
 
 struct SymArgs {
   const BunchDev* bunches;
   const SymItem* items;
   const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;
-  // partial slots of the rounds [r0, r0 + rounds): float index
+  // partial slots of the sub-rounds [r0, r0 + count): float index
   // (((r - r0) * nbt + block) * 2 + side) * SLOT_PLANES + plane) * block_size + offset,
-  // block = bunch's first block + I (side 0, receiver) or + J (side 1, source)
+  // block = bunch's first block + I (side 0, receiver) or + J (side 1, source);
+  // an item writes the source side only at the offsets of its part of J
   float* slot;
   int32_t r0;
   int32_t nbt;             // blocks over all bunches
+  int32_t split;           // items per block pair (1, 2 or 4)
   // near/far split (needs the spatial sort): a source group whose box is
   // farther than near_frac * min(U, (|a| + |b|) / 2) from a wavefront's receiver
   // box (a, b: the boxes' per-axis largest |coordinate|) uses plain FP32
@@ -117,8 +121,8 @@ struct SymArgs {
   const uint32_t* ubits;   // per-bunch bound U on |scaled coordinate| (float bits)
 };
 
-// Fold of the slots of rounds [r0, r1) into the accumulators (SYM_PLANES
-// planes of length n_total, indexed by position), in round order.
+// Fold of the slots of sub-rounds [r0, r1) into the accumulators (SYM_PLANES
+// planes of length n_total, indexed by position), in sub-round order.
 struct SymFoldArgs {
   const BunchDev* bunches;
   const int32_t* bid;
@@ -128,6 +132,7 @@ struct SymFoldArgs {
   int32_t r0, r1;
   int32_t nbt;
   int32_t block_size;
+  int32_t split;
 };
 
 // Spatial sort (pp_sort.hip): keys per tile of the radix sort.

@@ -21,7 +21,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <new>
+#include <queue>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -243,30 +245,34 @@ pp_status build_sym(pp_ctx* c) {
   pp_status st;
   set_sort_bits(c);
   const int64_t BS = c->sym_block();
+  const int64_t S = c->tun.sym_split;
+  // sub-round d * S + h holds part h of every block pair of round d (round 0:
+  // the diagonal blocks); round_first[v] is the first item of sub-round v
   std::vector<ppk::SymItem> items;
   std::vector<int64_t> round_first;
   int64_t maxr = 0;
-  round_first.push_back(0);
   for (int b = 0; b < c->nb; ++b) {
     const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
-    if (nbk > INT32_MAX / 2) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule: too many blocks");
-    for (int64_t I = 0; I < nbk; ++I) items.push_back({b, (int32_t)I, (int32_t)I, 0});
+    if (nbk > INT32_MAX / 8) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule: too many blocks");
     maxr = std::max(maxr, nbk / 2);
   }
-  for (int64_t d = 1; d <= maxr; ++d) {
-    round_first.push_back((int64_t)items.size());
-    for (int b = 0; b < c->nb; ++b) {
-      const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
-      if (d > nbk / 2) continue;
-      for (int64_t I = 0; I < nbk; ++I) {
-        if (2 * d == nbk && I >= nbk / 2) continue;
-        items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), (int32_t)d});
+  for (int64_t d = 0; d <= maxr; ++d) {
+    for (int64_t h = 0; h < S; ++h) {
+      round_first.push_back((int64_t)items.size());
+      const int32_t v = (int32_t)(d * S + h);
+      for (int b = 0; b < c->nb; ++b) {
+        const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
+        if (d > nbk / 2) continue;
+        for (int64_t I = 0; I < nbk; ++I) {
+          if (d > 0 && 2 * d == nbk && I >= nbk / 2) continue;
+          items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), v});
+        }
       }
     }
   }
   round_first.push_back((int64_t)items.size());
   if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
-  const int64_t rounds = maxr + 1;
+  const int64_t rounds = (maxr + 1) * S;
   const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * c->acc_elem();
   // the fewest bands that fit, of equal size (no short last band leaving the GPU half idle)
   const int64_t band_max = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
@@ -281,10 +287,11 @@ pp_status build_sym(pp_ctx* c) {
   // Launch order inside the first band: the diagonal items (about 0.6 of an
   // off-diagonal item's time) go last, so the cheapest items fill the tail of
   // the launch (longest-first list scheduling).  Items are independent and the
-  // fold adds slots in round order, so the order changes no result.
+  // fold adds slots in sub-round order, so the order changes no result.
   {
     const int64_t r1 = std::min(rounds, band);
-    std::rotate(items.begin() + round_first[0], items.begin() + round_first[1], items.begin() + round_first[r1]);
+    std::rotate(items.begin() + round_first[0], items.begin() + round_first[std::min(S, r1)],
+                items.begin() + round_first[r1]);
   }
   const size_t slot_need = (size_t)band * per_round;
   if (slot_need > c->slot_bytes) {
@@ -561,6 +568,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     sa.qt = c->qt64;
     sa.slot = (double*)c->slot;
     sa.nbt = c->n_blocks;
+    sa.split = c->tun.sym_split;
     ppk::SymFoldArgs64 fa{};
     fa.bunches = c->dbunch;
     fa.bid = c->bid;
@@ -569,6 +577,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     fa.acc = (double*)c->acc;
     fa.nbt = c->n_blocks;
     fa.block_size = (int32_t)c->sym_block();
+    fa.split = c->tun.sym_split;
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
@@ -587,6 +596,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     sa.qt = c->plane(6);
     sa.slot = (float*)c->slot;
     sa.nbt = c->n_blocks;
+    sa.split = c->tun.sym_split;
     if (c->far()) {
       ppk::SortArgs so{};
       so.bunches = c->dbunch;
@@ -630,6 +640,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     fa.acc = (float*)c->acc;
     fa.nbt = c->n_blocks;
     fa.block_size = (int32_t)c->sym_block();
+    fa.split = c->tun.sym_split;
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
@@ -742,7 +753,33 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   if (t.symmetric && k == 8) return false;
   // far_split <= 4 keeps the per-term bound 2 sqrt(3) 2^-23 2^f at 6.6e-6, inside the mixed tolerance
   if (t.far_split < 0 || t.far_split > 4 || (t.far_split > 0 && (!t.symmetric || !mixed))) return false;
+  // parts per block pair: a divisor of the 8 (mixed) or 4 (FP64) groups of a
+  // block at 1 receiver per lane
+  if (!(t.sym_split == 1 || t.sym_split == 2 || t.sym_split == 4)) return false;
   return true;
+}
+
+// Finish time of a greedy list schedule (each item to the earliest free slot,
+// in launch order: n_off items of cost c_off, then n_diag of cost c_diag) on
+// `slots` slots.  Beyond 64 items per slot the tail is bounded by one item.
+double list_makespan(double n_off, double c_off, double n_diag, double c_diag, double slots) {
+  const double total = n_off * c_off + n_diag * c_diag;
+  if (n_off + n_diag > 64.0 * slots) return total / slots + std::max(c_off, c_diag);
+  const int64_t P = (int64_t)slots;
+  std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+  for (int64_t k = 0; k < P; ++k) free_at.push(0.0);
+  double end = 0.0;
+  auto place = [&](int64_t n, double cost) {
+    for (int64_t k = 0; k < n; ++k) {
+      const double t = free_at.top() + cost;
+      free_at.pop();
+      free_at.push(t);
+      end = std::max(end, t);
+    }
+  };
+  place((int64_t)n_off, c_off);
+  place((int64_t)n_diag, c_diag);
+  return end;
 }
 
 // Default tiling from the bunch sizes.  The symmetric schedule (mixed: with
@@ -754,9 +791,20 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
 // at 4, 1.51 at 2, the FP64 sweep gaining less over its ordered kernel because
 // its r^-3 costs more relative to the rest of a pair and the fold of FP64
 // slots costs 2-4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
-// is left to the autotuner.  Padded blocks are paid in full, and the cost is
-// divided by the fill of the last wave of workgroups (items over resident
-// slots times the waves they need).
+// is left to the autotuner.  The mixed sweep loses ground in small bunches
+// (fewer wavefront boxes clear the far threshold, and the sort and the fold
+// weigh more): charged as 1 + 3 / (bunch size / 1024), and at 4 receivers per
+// lane, whose wider boxes suffer most (measured on uniform spheres: 1.27x at
+// 16 blocks, 1.19x at 32, 1.05x at 64, relative to 2 per lane), also
+// 1 + 4 / blocks.
+// Splitting each block pair into S items adds kSplitOverhead / BS of a block
+// pair's cost per extra item (receiver loads, slot stores, the fold's extra
+// reads; measured 1-4% per extra item at BS = 512-2048).  Padded blocks are
+// paid in full, and the cost is the finish time of the launch's list schedule
+// over the resident slots times the slot count (idle slots in the last wave
+// included).
+constexpr double kSplitOverhead = 24.0;
+
 pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   int64_t min_n = INT64_MAX;
   double ordered = 0.0;
@@ -771,6 +819,7 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   t.grid_per_cu = 4;
   t.graph_steps = 16;
   t.symmetric = 0;
+  t.sym_split = 1;
   struct Variant { int k; double bs, eff; int blocks_per_cu; };
   std::vector<Variant> vars;
   if (mixed) {
@@ -782,20 +831,37 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   }
   double best = ordered;
   for (const Variant& v : vars) {
-    double cost = 0.0, items = 0.0;
+    // pair-weighted small-bunch factor of the mixed sweep
+    double wsum = 0.0, psum = 0.0;
     for (const auto& b : hb) {
       const double nbk = std::ceil((double)b.n / v.bs);
-      cost += v.bs * v.bs * (0.6 * nbk + 1.02 * nbk * (nbk - 1.0) / 2.0) * v.eff;
-      items += nbk * (nbk + 1.0) / 2.0;
+      double f = 1.0;
+      if (mixed) {
+        f = 1.0 + 3.0 / std::ceil((double)b.n / (2.0 * ppk::SYM_WG));
+        if (v.k == 4) f *= 1.0 + 4.0 / nbk;
+      }
+      wsum += nbk * nbk * f;
+      psum += nbk * nbk;
     }
-    const double slots = (double)cus * v.blocks_per_cu;
-    const double fill = items / (slots * std::ceil(items / slots));
-    cost /= fill;
-    if (cost < best) {
-      best = cost;
-      t.symmetric = 1;
-      t.i_per_lane = v.k;
-      t.far_split = mixed ? 3 : 0;  // mixed: per-term change at most 3.3e-6 relative
+    const double eff = v.eff * wsum / psum;
+    for (int S : {1, 2, 4}) {
+      double n_off = 0.0, n_diag = 0.0;
+      for (const auto& b : hb) {
+        const double nbk = std::ceil((double)b.n / v.bs);
+        n_off += S * nbk * (nbk - 1.0) / 2.0;
+        n_diag += S * nbk;
+      }
+      const double unit = v.bs * v.bs * eff, extra = (S - 1) * (kSplitOverhead / v.bs) / S;
+      const double slots = (double)cus * v.blocks_per_cu;
+      const double cost =
+          slots * list_makespan(n_off, unit * (1.02 / S + extra), n_diag, unit * (0.6 / S + extra), slots);
+      if (cost < best) {
+        best = cost;
+        t.symmetric = 1;
+        t.i_per_lane = v.k;
+        t.sym_split = S;
+        t.far_split = mixed ? 3 : 0;  // mixed: per-term change at most 3.3e-6 relative
+      }
     }
   }
   return t;
@@ -810,7 +876,7 @@ pp_status apply_tuning(pp_ctx* c, const pp_tuning& t) {
 
 // ---------------------------------------------------------------------------
 // Autotuner: coordinate search over (i_per_lane, sum_tile, grid_per_cu,
-// chunk size, schedule, far split) by
+// chunk size, schedule, far split, split of block pairs) by
 // timed field evaluations on the context's own bunches; a candidate must
 // reproduce the field of the starting tiling (relative L2 within the
 // precision's tolerance) to be kept.  Choices are cached in a text file
@@ -821,7 +887,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v4";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v5";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -835,7 +901,7 @@ std::string tune_path() {
 }
 
 bool tune_lookup(const std::string& key, pp_tuning* t) {
-  // one record per line: key and the 7 tuning fields; other lines are skipped
+  // one record per line: key and the 8 tuning fields; other lines are skipped
   std::ifstream f(tune_path());
   std::string line;
   bool found = false;
@@ -844,7 +910,7 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
     std::string k, extra;
     pp_tuning v{};
     if (!(in >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
-          v.symmetric >> v.far_split) || (in >> extra))
+          v.symmetric >> v.far_split >> v.sym_split) || (in >> extra))
       continue;
     if (k == key) { *t = v; found = true; }
   }
@@ -869,7 +935,7 @@ void tune_store(const std::string& key, const pp_tuning& t) {
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
-      << t.graph_steps << " " << t.symmetric << " " << t.far_split << "\n";
+      << t.graph_steps << " " << t.symmetric << " " << t.far_split << " " << t.sym_split << "\n";
 }
 
 pp_status time_eval(pp_ctx* c, int reps, double* ms) {
@@ -971,6 +1037,11 @@ pp_status autotune(pp_ctx* c) {
       for (int f : {0, 2, 3, 4}) {
         pp_tuning t = best;
         t.far_split = f;
+        if ((s = trial(t)) != PP_OK) return s;
+      }
+      for (int sp : {1, 2, 4}) {
+        pp_tuning t = best;
+        t.sym_split = sp;
         if ((s = trial(t)) != PP_OK) return s;
       }
     }

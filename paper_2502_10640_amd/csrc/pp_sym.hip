@@ -201,7 +201,10 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     Sip[k] = Cip[k] = 0.f;
   }
 
-  for (int g = 0; g < BS / 64; ++g) {
+  // this item's part of source block J: groups [g0, g1) of its BS / 64
+  const int gpart = BS / 64 / a.split;
+  const int g0 = (it.r % a.split) * gpart, g1 = g0 + gpart;
+  for (int g = g0; g < g1; ++g) {
     const int jg = jbase0 + g * 64;
     __syncthreads();  // LDS of the previous group is free
     if (w == 0) {
@@ -297,7 +300,7 @@ template <int K, bool UQ, bool PHI>
 __global__ __launch_bounds__(SYM_WG) void pair_sym_kernel(SymArgs a, int32_t first) {
   __shared__ SymShared sh;
   const SymItem it = a.items[first + blockIdx.x];
-  if (it.r == 0)
+  if (it.r < a.split)
     sym_item<K, UQ, PHI, true>(a, it, sh);
   else
     sym_item<K, UQ, PHI, false>(a, it, sh);
@@ -315,8 +318,10 @@ hipError_t go_sym_k(const SymArgs& a, int32_t first, int32_t count, bool uq, boo
   return phi ? go_sym<K, false, true>(a, first, count, s) : go_sym<K, false, false>(a, first, count, s);
 }
 
-// One thread per position: adds the slots of rounds [r0, r1) in round order to
-// the accumulators; round 0 (diagonal items) starts them.
+// One thread per position: adds the slots of sub-rounds [r0, r1) in order to
+// the accumulators; sub-round 0 (the first part of the diagonal items) starts
+// them.  Receiver side: every part of a block pair; source side: only the part
+// that holds this position.
 template <bool PHI>
 __global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -346,13 +351,21 @@ __global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
     }
   }
   const int64_t sl = (int64_t)SLOT_PLANES * BS;
-  for (int r = a.r0; r < a.r1; ++r) {
-    const float* base = a.slot + ((int64_t)(r - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+  const int S = a.split, part = o / (BS / S);
+  for (int v = a.r0; v < a.r1; ++v) {
+    const float* base = a.slot + ((int64_t)(v - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+    const int r = v / S;
     if (r == 0) {
+      if (v == 0) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        rs[q] = base[(q < 3 ? q : 6) * BS];
-        rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+        for (int q = 0; q < NQ; ++q) {
+          rs[q] = base[(q < 3 ? q : 6) * BS];
+          rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          two_sum_pair(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
       }
       continue;
     }
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
     // even block count the round r = nbk / 2 holds only the items with I < nbk / 2.
     const bool has_r = !(2 * r == nbk && X >= half);
     const int js = X - r < 0 ? X - r + nbk : X - r;
-    const bool has_s = !(2 * r == nbk && js >= half);
+    const bool has_s = !(2 * r == nbk && js >= half) && v % S == part;
     if (has_r) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)

@@ -14,8 +14,9 @@ struct SymArgs64 {
   const SymItem* items;
   const double *x, *y, *z, *qt;
   double* slot;            // (((r - r0) * nbt + block) * 2 + side) * SLOT_PLANES + plane) * block_size + offset
-  int32_t r0;
+  int32_t r0;              // first sub-round of the launch (SymItem::r)
   int32_t nbt;
+  int32_t split;           // items per block pair (1, 2 or 4)
 };
 
 struct SymFoldArgs64 {
@@ -24,9 +25,10 @@ struct SymFoldArgs64 {
   int64_t n_total;
   const double* slot;
   double* acc;             // SYM_PLANES planes of length n_total
-  int32_t r0, r1;
+  int32_t r0, r1;          // sub-rounds
   int32_t nbt;
   int32_t block_size;
+  int32_t split;
 };
 
 // Wavefronts per item; a block is SYM64_WG * i_per_lane particles.  Four

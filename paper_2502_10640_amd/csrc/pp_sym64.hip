@@ -140,7 +140,10 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     Sip[k] = Cip[k] = 0.0;
   }
 
-  for (int g = 0; g < BS / 64; ++g) {
+  // this item's part of source block J: groups [g0, g1) of its BS / 64
+  const int gpart = BS / 64 / a.split;
+  const int g0 = (it.r % a.split) * gpart, g1 = g0 + gpart;
+  for (int g = g0; g < g1; ++g) {
     const int jg = jbase0 + g * 64;
     __syncthreads();  // LDS of the previous group is free
     if (w == 0) {
@@ -213,7 +216,7 @@ template <int K, bool UQ, bool PHI>
 __global__ __launch_bounds__(SYM64_WG) void pair_sym64_kernel(SymArgs64 a, int32_t first) {
   __shared__ SymShared64 sh;
   const SymItem it = a.items[first + blockIdx.x];
-  if (it.r == 0)
+  if (it.r < a.split)
     sym_item64<K, UQ, PHI, true>(a, it, sh);
   else
     sym_item64<K, UQ, PHI, false>(a, it, sh);
@@ -231,8 +234,10 @@ hipError_t go_sym64_k(const SymArgs64& a, int32_t first, int32_t count, bool uq,
   return phi ? go_sym64<K, false, true>(a, first, count, s) : go_sym64<K, false, false>(a, first, count, s);
 }
 
-// One thread per position: adds the slots of rounds [r0, r1) in round order
-// to the accumulators; round 0 (diagonal items) starts them.
+// One thread per position: adds the slots of sub-rounds [r0, r1) in order to
+// the accumulators; sub-round 0 (the first part of the diagonal items) starts
+// them.  Receiver side: every part of a block pair; source side: only the part
+// that holds this position.
 template <bool PHI>
 __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,13 +267,21 @@ __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
     }
   }
   const int64_t sl = (int64_t)SLOT_PLANES * BS;
-  for (int r = a.r0; r < a.r1; ++r) {
-    const double* base = a.slot + ((int64_t)(r - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+  const int S = a.split, part = o / (BS / S);
+  for (int v = a.r0; v < a.r1; ++v) {
+    const double* base = a.slot + ((int64_t)(v - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
+    const int r = v / S;
     if (r == 0) {
+      if (v == 0) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        rs[q] = base[(q < 3 ? q : 6) * BS];
-        rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+        for (int q = 0; q < NQ; ++q) {
+          rs[q] = base[(q < 3 ? q : 6) * BS];
+          rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          two_sum_pair64(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
       }
       continue;
     }
@@ -277,7 +290,7 @@ __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
     // block count the round r = nbk / 2 holds only the items with I < nbk / 2
     const bool has_r = !(2 * r == nbk && X >= half);
     const int js = X - r < 0 ? X - r + nbk : X - r;
-    const bool has_s = !(2 * r == nbk && js >= half);
+    const bool has_s = !(2 * r == nbk && js >= half) && v % S == part;
     if (has_r) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)

@@ -72,7 +72,7 @@ class Diag(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("i_per_lane", ctypes.c_int32), ("sum_tile", ctypes.c_int32), ("chunk_pairs_log2", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("symmetric", ctypes.c_int32),
-                ("far_split", ctypes.c_int32)]
+                ("far_split", ctypes.c_int32), ("sym_split", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,7 +85,7 @@ class Profile(ctypes.Structure):
 
 _LIB = None
 _VP = ctypes.c_void_p
-ABI_VERSION = 2  # PP_ABI_VERSION of include/pp.h
+ABI_VERSION = 3  # PP_ABI_VERSION of include/pp.h
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert pp.pp_abi_version() == 2
+    assert pp.pp_abi_version() == 3
 
 
 def test_destroy_null_and_last_error(lib):

@@ -126,8 +126,9 @@ def test_three_hundred_small_bunches(orc, sched):
     print(f"    worst relative L2 over the bunches {worst:.3e}", flush=True)
 
 
-RAGGED_TUNINGS = {"ordered": None, "symmetric": {"symmetric": 1, "i_per_lane": 1, "far_split": 0},
-                  "symmetric_k4": {"symmetric": 1, "i_per_lane": 4, "far_split": 0}}
+RAGGED_TUNINGS = {"ordered": None, "symmetric": {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 1},
+                  "symmetric_k4": {"symmetric": 1, "i_per_lane": 4, "far_split": 0, "sym_split": 1},
+                  "symmetric_k2_split4": {"symmetric": 1, "i_per_lane": 2, "far_split": 0, "sym_split": 4}}
 
 
 @pytest.mark.parametrize("sched", list(RAGGED_TUNINGS))
@@ -269,16 +270,22 @@ def test_push_equals_step_batched_bitwise(prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_batch_equals_separate_contexts_bitwise(prec):
-    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 0, "far_split": 0})
+    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 0, "far_split": 0, "sym_split": 1})
 
 
 def test_symmetric_far_batch_equals_separate_contexts_bitwise():
     # the sort keys, the coordinate bound, the boxes and the fold are all per bunch
-    _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "far_split": 3})
+    _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "far_split": 3, "sym_split": 1})
 
 
 def test_fp64_symmetric_batch_equals_separate_contexts_bitwise():
-    _batch_equals_separate("fp64", {"i_per_lane": 1, "symmetric": 1, "far_split": 0})
+    _batch_equals_separate("fp64", {"i_per_lane": 1, "symmetric": 1, "far_split": 0, "sym_split": 1})
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_split_symmetric_batch_equals_separate_contexts_bitwise(prec):
+    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 1, "far_split": 3 if prec == "mixed" else 0,
+                                  "sym_split": 2})
 
 
 def _batch_equals_separate(prec, tuning):
@@ -408,12 +415,16 @@ def _sym_bunches():
             mixed_charge_bunch(1500, seed=5), wl.workload("cold_sphere_2048", n_override=5)[0]]
 
 
-@pytest.mark.parametrize("prec,K", [("mixed", 1), ("mixed", 2), ("mixed", 4), ("fp64", 1), ("fp64", 2), ("fp64", 4)])
-def test_symmetric_field_parity(orc, prec, K):
+@pytest.mark.parametrize("prec,K,split", [("mixed", 1, 1), ("mixed", 2, 1), ("mixed", 4, 1), ("fp64", 1, 1),
+                                          ("fp64", 2, 1), ("fp64", 4, 1), ("mixed", 1, 4), ("mixed", 4, 2),
+                                          ("fp64", 1, 4), ("fp64", 4, 2)])
+def test_symmetric_field_parity(orc, prec, K, split):
+    # split > 1: each block pair (diagonal ones too) is swept as `split` items
+    # over parts of the source block, folded in a fixed order
     bunches = _sym_bunches()
-    say(f"symmetric field {prec} K={K} sizes={[b.n for b in bunches]}")
-    with Sim(bunches, prec, tuning={"symmetric": 1, "i_per_lane": K, "far_split": 0}) as sim:
-        assert sim.tuning()["symmetric"] == 1
+    say(f"symmetric field {prec} K={K} split={split} sizes={[b.n for b in bunches]}")
+    with Sim(bunches, prec, tuning={"symmetric": 1, "i_per_lane": K, "far_split": 0, "sym_split": split}) as sim:
+        assert sim.tuning()["symmetric"] == 1 and sim.tuning()["sym_split"] == split
         full = gpu_field(sim)
         for k, b in enumerate(bunches):
             sl = sim.bunch_slice(k)
@@ -473,11 +484,11 @@ def _far_bound(f):
     return 2.0 * math.sqrt(3.0) * 2.0 ** -23 * 2.0 ** f
 
 
-@pytest.mark.parametrize("K,far", [(1, 1), (2, 3), (4, 2)])
-def test_far_split_field_parity(orc, K, far):
+@pytest.mark.parametrize("K,far,split", [(1, 1, 1), (2, 3, 1), (4, 2, 1), (2, 3, 4)])
+def test_far_split_field_parity(orc, K, far, split):
     bunches = _far_bunches()
-    say(f"far split field K={K} far={far} sizes={[b.n for b in bunches]} gap=3")
-    base = {"symmetric": 1, "i_per_lane": K}
+    say(f"far split field K={K} far={far} split={split} sizes={[b.n for b in bunches]} gap=3")
+    base = {"symmetric": 1, "i_per_lane": K, "sym_split": split}
     with Sim(bunches, "mixed", tuning={**base, "far_split": far}, gap=3) as sim:
         assert sim.tuning()["far_split"] == far
         got_far = gpu_field(sim)
@@ -531,7 +542,10 @@ def test_far_split_tuning_rules():
     say("far split tuning validation")
     with Sim([b], "mixed") as sim:
         for bad in ({"symmetric": 0, "far_split": 2}, {"symmetric": 1, "i_per_lane": 1, "far_split": 5},
-                    {"symmetric": 1, "i_per_lane": 1, "far_split": -1}):
+                    {"symmetric": 1, "i_per_lane": 1, "far_split": -1},
+                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 3},
+                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 0},
+                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 8}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
             assert e.value.status == pp.PP_ERR_INVALID_ARG
@@ -563,10 +577,10 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     lines = cache.read_text().splitlines()
     assert lines[:2] == junk.splitlines() and len(lines) == 3
     line = lines[2].split()
-    assert len(line) == 8 and line[0].startswith("gfx950:")
+    assert len(line) == 9 and line[0].startswith("gfx950:")
     assert [int(v) for v in line[1:]] == [tuned[k] for k in ("i_per_lane", "sum_tile", "chunk_pairs_log2",
                                                                "grid_per_cu", "graph_steps", "symmetric",
-                                                               "far_split")]
+                                                               "far_split", "sym_split")]
     with Sim([b], "mixed") as sim:
         sim.step_batched(1, graph=False, autotune=True)
         assert sim.tuning() == tuned
@@ -586,7 +600,7 @@ def test_autotune_fp64_searches_both_schedules(orc, tmp_path, monkeypatch):
         got = gpu_field(sim)
         st = {k: sim.host(k) for k in ("x", "y", "z")}
     print(f"    tuning chosen: {tuned}", flush=True)
-    assert tuned["far_split"] == 0 and tuned["i_per_lane"] in (1, 2, 4)
+    assert tuned["far_split"] == 0 and tuned["i_per_lane"] in (1, 2, 4) and tuned["sym_split"] in (1, 2, 4)
     ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
     check_field(got, ref, TOL["fp64"], "autotuned fp64 tiling")
     assert len((tmp_path / "tune64.txt").read_text().splitlines()) == 1
