@@ -62,11 +62,14 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     p.add_argument("--cpu-threads", type=int, default=0,
                    help="oracle threads for --mode oracle (0: every host core)")
-    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper", "oracle"],
+    p.add_argument("--sizes", default="12288,16384,24576,32768,49152,65536,98304,131072",
+                   help="particle counts for --mode tilings")
+    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper", "oracle", "tilings"],
                    help="drift: run --steps steps in mixed and FP64 precision and report the total-energy drift "
                         "and the mixed-vs-FP64 energy gap every --every steps (no timing line); paper: the "
                         "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases); "
-                        "oracle: time only the CPU oracle on --cpu-threads threads (no GPU)")
+                        "oracle: time only the CPU oracle on --cpu-threads threads (no GPU); tilings: pair-stage time of "
+                        "the default tiling against the ordered kernel and the unsplit symmetric ones at --sizes")
     p.add_argument("--paper-cases", default="main,dt,np", help="subset of main,dt,np for --mode paper")
     p.add_argument("--every", type=int, default=20)
     p.add_argument("--precisions", default="mixed,fp64")
@@ -124,6 +127,39 @@ def oracle_only(a):
     print(json.dumps({"metric": "pair interactions/s (CPU oracle)", "value": base["value"],
                       "unit": base["unit"], "cpu_baseline": base,
                       "config": {"workload": a.workload, "n": bunches[0].n}}))
+
+
+def tilings(a):
+    """Pair-stage time per field evaluation (pp_time_field: sort, pair kernel
+    and fold, HIP events) of the default tiling and of the ordered kernel and
+    the unsplit symmetric tilings, for --workload at each of --sizes.  Each
+    context is warmed first; every case is timed twice, the minimum kept."""
+    from paper_2502_10640_amd import pp
+    from paper_2502_10640_amd import workloads as wl
+    from paper_2502_10640_amd.sim import Simulation
+    for prec in a.precisions.split(","):
+        for n in (int(x) for x in a.sizes.split(",")):
+            bunches = wl.workload(a.workload, n_override=n)
+            with Simulation(bunches, prec) as sim:
+                d = sim.tuning()
+                reps = max(3, min(50, int(4e10 / n ** 2)))
+                pp.pp_time_field(sim.ctx, 3 * reps)
+                cands = [("default", d),
+                         ("ordered", {**d, "symmetric": 0, "far_split": 0, "sym_split": 1,
+                                      "i_per_lane": 2 if (prec == "mixed" and n >= 16384) else 1})]
+                for k in (2, 4):
+                    cands.append((f"symmetric K={k} split 1", {**d, "symmetric": 1, "i_per_lane": k, "sym_split": 1,
+                                                                "far_split": 3 if prec == "mixed" else 0}))
+                best = {}
+                for _ in range(2):
+                    for name, t in cands:
+                        sim.set_tuning(**t)
+                        pp.pp_time_field(sim.ctx, 2)
+                        ms, _ = pp.pp_time_field(sim.ctx, reps)
+                        best[name] = min(best.get(name, float("inf")), ms)
+            print(json.dumps({"mode": "tilings", "workload": a.workload, "precision": prec, "n": n,
+                              "default_tuning": {k: d[k] for k in ("symmetric", "i_per_lane", "sym_split", "far_split")},
+                              "pair_stage_ms": best}), flush=True)
 
 
 def total_energy(sim):
@@ -276,6 +312,9 @@ def main():
         return
     if a.mode == "oracle":
         oracle_only(a)
+        return
+    if a.mode == "tilings":
+        tilings(a)
         return
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)

@@ -457,6 +457,25 @@ def test_symmetric_push_graph_and_trajectory(orc, prec, K):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_default_tiling_splits_mid_size_bunches(orc, prec):
+    """A 32768-particle bunch has too few block pairs to fill the last wave of
+    items unsplit (16-32 blocks): the cost model splits them; at 12288 the
+    ordered kernel stays cheaper.  The split default reproduces the field."""
+    say(f"default tiling at 12288 and 32768 particles, {prec}")
+    with Sim(wl.workload("cold_sphere_1m", n_override=12288), prec) as sim:
+        assert sim.tuning()["symmetric"] == 0
+    b = wl.workload("cold_sphere_1m", n_override=32768)[0]
+    with Sim([b], prec) as sim:
+        t = sim.tuning()
+        assert t["symmetric"] == 1 and t["sym_split"] > 1, t
+        got = gpu_field(sim)
+    rng = np.random.default_rng(11)
+    recv = np.sort(rng.choice(b.n, 256, replace=False))
+    ref = orc.field(b.x, b.y, b.z, b.q, b.weight, b.softening, recv=recv, want_phi=True, want_amag=True)
+    check_field({k: v[recv] for k, v in got.items()}, ref, TOL[prec], f"default split {prec} n={b.n}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_symmetric_equals_itself_run_to_run(prec):
     b = wl.workload("cold_sphere_2048")[0]
     say(f"symmetric run-to-run bitwise {prec}")
