@@ -793,10 +793,11 @@ double list_makespan(double n_off, double c_off, double n_diag, double c_diag, d
 // slots costs 2-4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
 // is left to the autotuner.  The mixed sweep loses ground in small bunches
 // (fewer wavefront boxes clear the far threshold, and the sort and the fold
-// weigh more): charged as 1 + 3 / (bunch size / 1024), and at 4 receivers per
-// lane, whose wider boxes suffer most (measured on uniform spheres: 1.27x at
-// 16 blocks, 1.19x at 32, 1.05x at 64, relative to 2 per lane), also
-// 1 + 4 / blocks.
+// weigh more): charged as 1 + 3 / (bunch size / 1024).  At 4 receivers per
+// lane it also loses at small launches (measured on single uniform spheres:
+// 1.27x at 16 blocks, 1.19x at 32, 1.05x at 64, relative to 2 per lane, but
+// not in a batch of 64 such bunches), charged as 1 + 4 / B with B the root
+// of the sum of squared block counts (the block count of a single bunch).
 // Splitting each block pair into S items adds kSplitOverhead / BS of a block
 // pair's cost per extra item (receiver loads, slot stores, the fold's extra
 // reads; measured 1-4% per extra item at BS = 512-2048).  Padded blocks are
@@ -835,15 +836,12 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
     double wsum = 0.0, psum = 0.0;
     for (const auto& b : hb) {
       const double nbk = std::ceil((double)b.n / v.bs);
-      double f = 1.0;
-      if (mixed) {
-        f = 1.0 + 3.0 / std::ceil((double)b.n / (2.0 * ppk::SYM_WG));
-        if (v.k == 4) f *= 1.0 + 4.0 / nbk;
-      }
+      const double f = mixed ? 1.0 + 3.0 / std::ceil((double)b.n / (2.0 * ppk::SYM_WG)) : 1.0;
       wsum += nbk * nbk * f;
       psum += nbk * nbk;
     }
-    const double eff = v.eff * wsum / psum;
+    double eff = v.eff * wsum / psum;
+    if (mixed && v.k == 4) eff *= 1.0 + 4.0 / std::sqrt(psum);
     for (int S : {1, 2, 4}) {
       double n_off = 0.0, n_diag = 0.0;
       for (const auto& b : hb) {

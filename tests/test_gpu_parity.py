@@ -406,6 +406,21 @@ def test_full_size_sampled_parity_cold_sphere_1m(orc, prec):
     check_field(got, ref, TOL[prec], f"cold_sphere_1m/{prec} sampled")
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_split_with_many_slot_bands_sampled_parity_1m(orc, prec):
+    """Block pairs split in 2 at 1 048 576 particles: the sub-rounds' slots
+    exceed one 8 GiB band (5 bands mixed, 17 FP64), so the fold carries the
+    accumulators across bands and the diagonal items sit in the first one."""
+    b = wl.workload("cold_sphere_1m")[0]
+    rng = np.random.default_rng(98)
+    recv = np.sort(rng.choice(b.n, 256, replace=False))
+    tun = {"symmetric": 1, "i_per_lane": 4, "sym_split": 2, "far_split": 3 if prec == "mixed" else 0}
+    say(f"split 2 with slot bands, cold_sphere_1m {prec}")
+    with Sim([b], prec, tuning=tun) as sim:
+        got = gpu_field(sim, sl=recv)
+    check_field(got, oracle_field(orc, b, recv=recv), TOL[prec], f"cold_sphere_1m/{prec} split 2 sampled")
+
+
 # ---------------------------------------------------------------------------
 # symmetric (one rsq per unordered pair) schedule
 # ---------------------------------------------------------------------------
