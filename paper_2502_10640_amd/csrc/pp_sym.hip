@@ -25,7 +25,10 @@
 // item writes slots of its own, so the items of many rounds run in one launch
 // in any order; the fold kernel then adds the slots of each position in round
 // order (receiver side and source side kept apart), which fixes the order of
-// every addition.
+// every addition.  With block pairs split in S parts (for bunches too small
+// to fill the last wave of items), round r becomes sub-rounds r S + h and
+// item h sweeps only part h of source block J's groups: a full receiver-side
+// slot, the source-side slot at the offsets of its part only.
 #include "pp_device.h"
 #include "pp_internal.h"
 

@@ -9,8 +9,10 @@
 // source-side partial follows its source one lane down per step (two
 // ds_bpermute per double), arriving at the source's home lane after the 64th
 // step.  r^-3 comes from v_rsq_f64 and one third-order series correction
-// (inv_r3_64).  Items write FP64 partial slots indexed (round, block, side); the
-// fold adds them in round order, so every addition has a fixed order.
+// (inv_r3_64).  Items write FP64 partial slots indexed (sub-round, block,
+// side); the fold adds them in sub-round order, so every addition has a fixed
+// order.  A sub-round r S + h is part h of round r when block pairs are split
+// in S parts of the source block's groups (S = 1: plain rounds).
 //
 // Positions are the unscaled FP64 state and separations are plain FP64
 // differences (no hi/lo split and no spatial sort are needed at this
