@@ -447,12 +447,12 @@ def test_symmetric_field_parity(orc, prec, K, split):
             check_field(got, oracle_field(orc, b), TOL[prec], f"sym {prec} K={K} n={b.n}")
 
 
-@pytest.mark.parametrize("K", [1, 4])
+@pytest.mark.parametrize("K,split", [(1, 1), (4, 1), (1, 4)])
 @pytest.mark.parametrize("prec", PRECS)
-def test_symmetric_push_graph_and_trajectory(orc, prec, K):
+def test_symmetric_push_graph_and_trajectory(orc, prec, K, split):
     b = wl.workload("gaussian_65536", n_override=2500)[0]
-    say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}, K={K}")
-    tun = {"symmetric": 1, "i_per_lane": K, "graph_steps": 3}
+    say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}, K={K} split={split}")
+    tun = {"symmetric": 1, "i_per_lane": K, "graph_steps": 3, "sym_split": split}
     res = []
     for mode in ("push", "graph"):
         with Sim([b], prec, tuning=tun) as sim:
@@ -548,10 +548,11 @@ def test_far_split_field_parity(orc, K, far, split):
     assert changed >= 1  # the far path ran
 
 
-def test_far_split_push_graph_run_to_run_and_trajectory(orc):
+@pytest.mark.parametrize("split", [1, 2])
+def test_far_split_push_graph_run_to_run_and_trajectory(orc, split):
     b = wl.workload("gaussian_65536", n_override=9000)[0]
-    say("far split push == step_batched(graph), run-to-run, trajectory vs oracle, 6 steps")
-    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3, "graph_steps": 2}
+    say(f"far split push == step_batched(graph), run-to-run, trajectory vs oracle, 6 steps, split={split}")
+    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3, "graph_steps": 2, "sym_split": split}
     res = []
     for mode in ("push", "graph", "push"):
         with Sim([b], "mixed", tuning=tun) as sim:
