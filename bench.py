@@ -223,7 +223,10 @@ PAPER_WALL_S = 532.0  # the paper's time for its 16^3 case, 100 000 steps, 64 EP
 
 def run_series(sim, n_steps, every):
     """Step n_steps (hipGraph replay) with diagnostics every `every` steps;
-    returns the wall time of the stepping alone and the per-bunch series."""
+    returns the wall time of the stepping alone and the per-bunch series.
+    The context's graphs should be long (paper_tuning): each replay costs
+    ~10 us of launch gap, 3% of a step of the 4096-particle cube at 16 steps
+    per graph."""
     import torch
     series = [[] for _ in sim.bunches]
 
@@ -243,6 +246,13 @@ def run_series(sim, n_steps, every):
         done += k
         record()
     return t_run, series
+
+
+def paper_tuning(every):
+    """hipGraphs of up to 200 steps (a multiple of the far split's 8-step
+    resort cadence), or one diagnostics interval if that is shorter: longer
+    graphs save little more and cost more to instantiate."""
+    return {"graph_steps": max(1, min(200, every))}
 
 
 def paper(a):
@@ -273,8 +283,9 @@ def paper(a):
             b = wl.paper_cube(16)
             n_steps = int(round(PAPER_T_END / b.dt))
             print(f"[paper] 16^3 {prec}: {n_steps} steps", file=sys.stderr, flush=True)
-            with Simulation([b], prec) as sim:
-                t_run, ser = run_series(sim, n_steps, int(round(1e-10 / b.dt)))
+            every = int(round(1e-10 / b.dt))
+            with Simulation([b], prec, tuning=paper_tuning(every)) as sim:
+                t_run, ser = run_series(sim, n_steps, every)
             out["cases"][f"main_{prec}"] = summary([b], prec, b.dt, ser, t_run, n_steps)
         m, f = out["cases"]["main_mixed"], out["cases"]["main_fp64"]
         em, ef = np.array(m["emittance_x"][0]), np.array(f["emittance_x"][0])
@@ -285,15 +296,17 @@ def paper(a):
             b = wl.paper_cube(16, dt=dt)
             n_steps = int(round(PAPER_T_END / dt))
             print(f"[paper] dt sweep dt={dt:g}: {n_steps} steps", file=sys.stderr, flush=True)
-            with Simulation([b], "mixed") as sim:
-                t_run, ser = run_series(sim, n_steps, max(1, int(round(1e-10 / dt))))
+            every = max(1, int(round(1e-10 / dt)))
+            with Simulation([b], "mixed", tuning=paper_tuning(every)) as sim:
+                t_run, ser = run_series(sim, n_steps, every)
             out["cases"][f"dt_{dt:g}"] = summary([b], "mixed", dt, ser, t_run, n_steps)
     if "np" in cases:
         bunches = wl.workload("paper_np_batch")
         n_steps = int(round(PAPER_T_END / bunches[0].dt))
         print(f"[paper] N_p sweep as one batch: {n_steps} steps", file=sys.stderr, flush=True)
-        with Simulation(bunches, "mixed") as sim:
-            t_run, ser = run_series(sim, n_steps, int(round(1e-10 / bunches[0].dt)))
+        every = int(round(1e-10 / bunches[0].dt))
+        with Simulation(bunches, "mixed", tuning=paper_tuning(every)) as sim:
+            t_run, ser = run_series(sim, n_steps, every)
         out["cases"]["np_batch"] = summary(bunches, "mixed", bunches[0].dt, ser, t_run, n_steps)
     print(json.dumps(out))
 
