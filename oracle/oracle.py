@@ -74,7 +74,7 @@ class Oracle:
         self.lib = ctypes.CDLL(lib_path)
         L = self.lib
         L.oracle_field.argtypes = [ctypes.c_int64, _P, _P, _P, _P, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_int64, _PI, _P, _P, _P, _P, _P]
+                                   ctypes.c_double, ctypes.c_int64, _PI, _P, _P, _P, _P, _P, _P]
         L.oracle_field.restype = None
         L.oracle_vv.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -115,8 +115,9 @@ class Oracle:
         self.lib.oracle_set_num_threads(int(n))
 
     def field(self, x, y, z, q, w: float, eps: float, recv=None, want_phi=False,
-              want_amag=False):
-        """E (and optionally phi, A) at receivers ``recv`` (all if None)."""
+              want_amag=False, want_pmag=False):
+        """E (and optionally phi, A, P) at receivers ``recv`` (all if None).
+        A and P are the sums of the magnitudes of the terms of E and of phi."""
         x = self._arr(x)
         n = x.shape[0]
         y, z, q = self._arr(y, n), self._arr(z, n), self._arr(q, n)
@@ -130,15 +131,19 @@ class Oracle:
         ex, ey, ez = (np.empty(nr) for _ in range(3))
         phi = np.empty(nr) if want_phi else None
         amag = np.empty(nr) if want_amag else None
+        pmag = np.empty(nr) if want_pmag else None
         self.lib.oracle_field(n, self._d(x), self._d(y), self._d(z), self._d(q), w, eps, nr, rp,
                               self._d(ex), self._d(ey), self._d(ez),
                               self._d(phi) if phi is not None else None,
-                              self._d(amag) if amag is not None else None)
+                              self._d(amag) if amag is not None else None,
+                              self._d(pmag) if pmag is not None else None)
         out = {"ex": ex, "ey": ey, "ez": ez}
         if want_phi:
             out["phi"] = phi
         if want_amag:
             out["amag"] = amag
+        if want_pmag:
+            out["pmag"] = pmag
         return out
 
     def vv(self, state: "OracleState", n_steps: int) -> None:

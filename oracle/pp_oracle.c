@@ -11,7 +11,8 @@
  *   oracle_field  -- the direct field sum of Eq. (B) (Coulomb's law Eq. (A)
  *                    summed over all j != i), with Plummer softening eps
  *                    (eps = 0 gives Eq. (B) exactly), the matching potential
- *                    and the sum of term magnitudes used for error metrics.
+ *                    and, for error metrics, the sums of the magnitudes of the
+ *                    field's and of the potential's terms.
  *   oracle_vv     -- the Velocity Verlet integrator of Eqs. (G) and (H), with
  *                    the acceleration a = (q/m) E of Eqs. (D)/(F).
  *   oracle_diag   -- energies, momentum, centre of mass and the beam moments
@@ -60,7 +61,10 @@ static void neumaier_add(double *s, double *c, double v) {
  *   E_i   = k sum_{j != i} (w q_j) (r_i - r_j) / (|r_i - r_j|^2 + eps^2)^(3/2)
  *   phi_i = k sum_{j != i} (w q_j) / (|r_i - r_j|^2 + eps^2)^(1/2)
  *   A_i   = k sum_{j != i} |w q_j| |r_i - r_j| / (|r_i - r_j|^2 + eps^2)^(3/2)
- * The separation vector is r_ij = r_i - r_j as Eq. (A) defines it, so like
+ *   P_i   = k sum_{j != i} |w q_j| / (|r_i - r_j|^2 + eps^2)^(1/2)
+ * A_i is the sum of the magnitudes of the terms of E_i and P_i that of the
+ * terms of phi_i: what the sums had to cancel, the scale of a per-particle
+ * error.  The separation vector is r_ij = r_i - r_j as Eq. (A) defines it, so like
  * charges repel.  The self term j = i is excluded by index, as the sum in
  * Eq. (B) states, whatever eps is.
  *
@@ -71,12 +75,12 @@ static void neumaier_add(double *s, double *c, double v) {
  *             (then n_recv must equal n), else recv[k] is the index of the
  *             k-th receiver
  * ex,ey,ez    out, length n_recv [V/m]
- * phi, amag   out, length n_recv, may be NULL
+ * phi, amag, pmag   out, length n_recv, may be NULL
  */
 void oracle_field(int64_t n, const double *x, const double *y, const double *z,
                   const double *q, double w, double eps, int64_t n_recv,
                   const int64_t *recv, double *ex, double *ey, double *ez,
-                  double *phi, double *amag) {
+                  double *phi, double *amag, double *pmag) {
   const double k = coulomb_k();
   const double eps2 = eps * eps;
   int64_t r;
@@ -84,7 +88,7 @@ void oracle_field(int64_t n, const double *x, const double *y, const double *z,
   for (r = 0; r < n_recv; ++r) {
     const int64_t i = recv ? recv[r] : r;
     double sx = 0, cx = 0, sy = 0, cy = 0, sz = 0, cz = 0;
-    double sp = 0, cp = 0, sa = 0, ca = 0;
+    double sp = 0, cp = 0, sa = 0, ca = 0, sb = 0, cb = 0;
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
       const double dx = x[i] - x[j];
@@ -100,12 +104,14 @@ void oracle_field(int64_t n, const double *x, const double *y, const double *z,
       neumaier_add(&sz, &cz, qj * dz * inv3);
       if (phi) neumaier_add(&sp, &cp, qj * inv);
       if (amag) neumaier_add(&sa, &ca, fabs(qj) * sqrt(d2) * inv3);
+      if (pmag) neumaier_add(&sb, &cb, fabs(qj) * inv);
     }
     ex[r] = k * (sx + cx);
     ey[r] = k * (sy + cy);
     ez[r] = k * (sz + cz);
     if (phi) phi[r] = k * (sp + cp);
     if (amag) amag[r] = k * (sa + ca);
+    if (pmag) pmag[r] = k * (sb + cb);
   }
 }
 
@@ -113,7 +119,7 @@ void oracle_field(int64_t n, const double *x, const double *y, const double *z,
 static void accel(int64_t n, const double *x, const double *y, const double *z,
                   const double *q, const double *m, double w, double eps,
                   double *ax, double *ay, double *az) {
-  oracle_field(n, x, y, z, q, w, eps, n, NULL, ax, ay, az, NULL, NULL);
+  oracle_field(n, x, y, z, q, w, eps, n, NULL, ax, ay, az, NULL, NULL, NULL);
   for (int64_t i = 0; i < n; ++i) {
     const double qm = q[i] / m[i];
     ax[i] *= qm;
@@ -209,7 +215,7 @@ void oracle_diag(int64_t n, const double *x, const double *y, const double *z,
     t[i] = 0.5 * w * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
   out->kinetic = csum(n, t);
 
-  oracle_field(n, x, y, z, q, w, eps, n, NULL, ex, ey, ez, phi, NULL);
+  oracle_field(n, x, y, z, q, w, eps, n, NULL, ex, ey, ez, phi, NULL, NULL);
   for (int64_t i = 0; i < n; ++i) t[i] = 0.5 * w * q[i] * phi[i];
   out->potential = csum(n, t);
   out->total = out->kinetic + out->potential;

@@ -13,7 +13,7 @@ import pytest
 from oracle.oracle import OracleState, default
 from paper_2502_10640_amd import pp
 from paper_2502_10640_amd import workloads as wl
-from tests._metrics import cond_max, l2_rel, vec
+from tests._metrics import cond_max, l2_rel, phi_cond_max, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -53,18 +53,23 @@ def gpu_field(sim, sl=None, phi=True):
 
 
 def oracle_field(orc, b, recv=None):
-    return orc.field(b.x, b.y, b.z, b.q, b.weight, b.softening, recv=recv, want_phi=True, want_amag=True)
+    return orc.field(b.x, b.y, b.z, b.q, b.weight, b.softening, recv=recv, want_phi=True, want_amag=True,
+                     want_pmag=True)
 
 
 def check_field(got, ref, tol, label):
+    """Field: relative L2 and the condition-aware max; potential (when both
+    sides have it): relative L2 and the per-particle max of |dphi_i| / P_i."""
     G, R = vec(got), vec(ref)
     e_l2 = l2_rel(G, R)
     e_cm = cond_max(G, R, ref["amag"])
     e_phi = l2_rel(got["phi"], ref["phi"]) if "phi" in got else 0.0
-    print(f"    {label}: l2={e_l2:.3e} cond_max={e_cm:.3e} phi_l2={e_phi:.3e}", flush=True)
+    e_pcm = phi_cond_max(got["phi"], ref["phi"], ref["pmag"]) if "phi" in got and "pmag" in ref else 0.0
+    print(f"    {label}: l2={e_l2:.3e} cond_max={e_cm:.3e} phi_l2={e_phi:.3e} phi_cond_max={e_pcm:.3e}", flush=True)
     assert e_l2 <= tol, (label, e_l2)
     assert e_cm <= tol, (label, e_cm)
     assert e_phi <= tol, (label, e_phi)
+    assert e_pcm <= tol, (label, e_pcm)
     return e_l2, e_cm
 
 
@@ -123,6 +128,7 @@ def test_three_hundred_small_bunches(orc, sched):
         e = l2_rel(vec(got), vec(ref))
         worst = max(worst, e)
         assert e <= TOL["mixed"] and cond_max(vec(got), vec(ref), ref["amag"]) <= TOL["mixed"], (k, b.n, e)
+        assert phi_cond_max(got["phi"], ref["phi"], ref["pmag"]) <= TOL["mixed"], (k, b.n)
     print(f"    worst relative L2 over the bunches {worst:.3e}", flush=True)
 
 
@@ -486,7 +492,8 @@ def test_default_tiling_splits_mid_size_bunches(orc, prec):
         got = gpu_field(sim)
     rng = np.random.default_rng(11)
     recv = np.sort(rng.choice(b.n, 256, replace=False))
-    ref = orc.field(b.x, b.y, b.z, b.q, b.weight, b.softening, recv=recv, want_phi=True, want_amag=True)
+    ref = orc.field(b.x, b.y, b.z, b.q, b.weight, b.softening, recv=recv, want_phi=True, want_amag=True,
+                    want_pmag=True)
     check_field({k: v[recv] for k, v in got.items()}, ref, TOL[prec], f"default split {prec} n={b.n}")
 
 
@@ -607,7 +614,8 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
         got = gpu_field(sim)
         st = {k: sim.host(k) for k in ("x", "y", "z")}
     print(f"    tuning chosen: {tuned}", flush=True)
-    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
+    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True,
+                    want_pmag=True)
     check_field(got, ref, TOL["mixed"], "autotuned tiling")
     lines = cache.read_text().splitlines()
     assert lines[:2] == junk.splitlines() and len(lines) == 3
@@ -636,7 +644,8 @@ def test_autotune_fp64_searches_both_schedules(orc, tmp_path, monkeypatch):
         st = {k: sim.host(k) for k in ("x", "y", "z")}
     print(f"    tuning chosen: {tuned}", flush=True)
     assert tuned["far_split"] == 0 and tuned["i_per_lane"] in (1, 2, 4) and tuned["sym_split"] in (1, 2, 4)
-    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True)
+    ref = orc.field(st["x"], st["y"], st["z"], b.q, b.weight, b.softening, want_phi=True, want_amag=True,
+                    want_pmag=True)
     check_field(got, ref, TOL["fp64"], "autotuned fp64 tiling")
     assert len((tmp_path / "tune64.txt").read_text().splitlines()) == 1
 
@@ -701,6 +710,7 @@ def test_full_size_sampled_parity_sweep_64(orc):
         worst = (max(worst[0], e[0]), max(worst[1], e[1]))
         assert e[0] <= TOL["mixed"] and e[1] <= TOL["mixed"], (k, b.n, e)
         assert l2_rel(got["phi"], ref["phi"]) <= TOL["mixed"], k
+        assert phi_cond_max(got["phi"], ref["phi"], ref["pmag"]) <= TOL["mixed"], k
     print(f"    sweep_64 worst over bunches: l2={worst[0]:.3e} cond_max={worst[1]:.3e}", flush=True)
 
 

@@ -26,12 +26,17 @@ MUTANTS = {
     "potential energy double counted": ("t[i] = 0.5 * w * q[i] * phi[i];", "t[i] = w * q[i] * phi[i];"),
     "kinetic energy without weight": ("0.5 * w * m[i] * (vx[i] * vx[i]", "0.5 * m[i] * (vx[i] * vx[i]"),
     "momentum without weight": ("t[i] = w * m[i] * v[a][i];", "t[i] = m[i] * v[a][i];"),
+    "field magnitude sum drops |r_ij|": ("fabs(qj) * sqrt(d2) * inv3", "fabs(qj) * inv3"),
+    "field magnitude sum drops |q|": ("fabs(qj) * sqrt(d2) * inv3", "qj * sqrt(d2) * inv3"),
+    "potential magnitude sum drops |q|": ("fabs(qj) * inv);", "qj * inv);"),
+    "potential magnitude sum drops softening": ("fabs(qj) * inv);", "fabs(qj) / sqrt(d2));"),
 }
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
 PIN_FUNCS = [
     pins.test_electron_field_at_one_micron,
+    pins.test_two_charges_term_magnitudes_closed_form,
     lambda o: [pins.test_symmetric_polyhedra_closed_forms(o, s) for s in ("tetrahedron", "octahedron", "cube")],
     lambda o: [pins.test_brute_force_50_digits(o, e) for e in (0.0, 2e-7)],
     pins.test_force_is_minus_gradient_of_potential,

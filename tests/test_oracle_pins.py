@@ -68,6 +68,28 @@ def test_electron_field_at_one_micron(orc):
     assert f["phi"][0] == approx(-1.4399645478e-3, rel=1e-9)
 
 
+def test_two_charges_term_magnitudes_closed_form(orc):
+    """One pair of unlike charges with softening: at each particle the sum of
+    the field terms' magnitudes is A = k |w q_j| d / (d^2 + eps^2)^(3/2) and that
+    of the potential terms P = k |w q_j| / (d^2 + eps^2)^(1/2) (Sec. 2.1,
+    Eq. (A) for one term).  Catches a magnitude sum that drops |r_ij|, drops the
+    absolute value of the charge or drops the softening; the potential itself
+    must keep the sign of the source charge."""
+    k = 1.0 / (4.0 * math.pi * wl.EPS0)
+    d, eps, w = 3e-6, 1.25e-6, 2.5
+    qs = np.array([-E, 3.0 * E])
+    f = _field(orc, [[0, 0, 0], [0, d, 0]], qs, w=w, eps=eps, want_phi=True, want_amag=True, want_pmag=True)
+    s2 = d * d + eps * eps
+    for i, j in ((0, 1), (1, 0)):
+        assert f["amag"][i] == approx(k * abs(w * qs[j]) * d / s2 ** 1.5, rel=1e-14)
+        assert f["pmag"][i] == approx(k * abs(w * qs[j]) / math.sqrt(s2), rel=1e-14)
+        assert f["phi"][i] == approx(k * w * qs[j] / math.sqrt(s2), rel=1e-14)
+    assert f["phi"][1] < 0 < f["pmag"][1]
+    # |E| equals A for a single term
+    mag = np.linalg.norm(_vec(f), axis=1)
+    np.testing.assert_allclose(mag, f["amag"], rtol=1e-14, atol=0)
+
+
 @pytest.mark.parametrize("shape", ["tetrahedron", "octahedron", "cube"])
 def test_symmetric_polyhedra_closed_forms(orc, shape):
     """Equidistant vertex sets with centroid at the origin: radial field
@@ -84,14 +106,20 @@ def test_symmetric_polyhedra_closed_forms(orc, shape):
     else:
         pos = np.array([[i, j, k] for i in (-.5, .5) for j in (-.5, .5) for k in (-.5, .5)]) * a
         C = CF["cube_side_a"]["C"]
+    key = {"tetrahedron": "tetrahedron_side_a", "octahedron": "octahedron_vertex_s", "cube": "cube_side_a"}[shape]
+    CA, CP = CF[key]["CA"], CF[key]["CP"]
     Q = 2 * E
-    f = _field(orc, pos, 2 * E, w=1.0)
+    f = _field(orc, pos, 2 * E, w=1.0, want_phi=True, want_amag=True, want_pmag=True)
     v = _vec(f)
     k = orc.k
     mag = np.linalg.norm(v, axis=1)
     np.testing.assert_allclose(mag, C * k * Q / a ** 2, rtol=1e-13)
     rhat = pos / np.linalg.norm(pos, axis=1, keepdims=True)
     np.testing.assert_allclose(v / mag[:, None], rhat, atol=1e-13)  # outward for Q > 0
+    # sums of the terms' magnitudes, and the potential (all terms of one sign)
+    np.testing.assert_allclose(f["amag"], CA * k * Q / a ** 2, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(f["pmag"], CP * k * Q / a, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(f["phi"], CP * k * Q / a, rtol=1e-13, atol=0)
 
 
 def _decimal_field(pos, q, w, eps, prec=50):
@@ -101,18 +129,26 @@ def _decimal_field(pos, q, w, eps, prec=50):
     P = [[Decimal(float(c)) for c in p] for p in pos]
     Qd = [Decimal(float(x)) * Decimal(float(w)) for x in q]
     e2 = Decimal(float(eps)) ** 2
-    out = []
+    out, amag, pmag, phi = [], [], [], []
     for i in range(len(P)):
         acc = [Decimal(0)] * 3
+        am, pm, ph = Decimal(0), Decimal(0), Decimal(0)
         for j in range(len(P)):
             if i == j:
                 continue
             d = [P[i][c] - P[j][c] for c in range(3)]
-            s = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + e2).sqrt()
+            r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+            s = (r2 + e2).sqrt()
             f = Qd[j] / (s * s * s)
             acc = [acc[c] + f * d[c] for c in range(3)]
+            am += abs(Qd[j]) * r2.sqrt() / (s * s * s)
+            pm += abs(Qd[j]) / s
+            ph += Qd[j] / s
         out.append([float(k * a) for a in acc])
-    return np.array(out)
+        amag.append(float(k * am))
+        pmag.append(float(k * pm))
+        phi.append(float(k * ph))
+    return np.array(out), np.array(amag), np.array(pmag), np.array(phi)
 
 
 @pytest.mark.parametrize("eps", [0.0, 2e-7])
@@ -123,10 +159,14 @@ def test_brute_force_50_digits(orc, eps):
     n = 13
     pos = rng.normal(size=(n, 3)) * 1e-6
     q = rng.choice([-1.0, 1.0, 2.0], size=n) * E
-    f = _field(orc, pos, q, w=3.5, eps=eps, want_amag=True)
-    ref = _decimal_field(pos, q, 3.5, eps)
-    err = np.abs(_vec(f) - ref).max(axis=1) / f["amag"]
+    f = _field(orc, pos, q, w=3.5, eps=eps, want_phi=True, want_amag=True, want_pmag=True)
+    ref, ref_amag, ref_pmag, ref_phi = _decimal_field(pos, q, 3.5, eps)
+    # the magnitude sums themselves, then each output relative to its own scale
+    np.testing.assert_allclose(f["amag"], ref_amag, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(f["pmag"], ref_pmag, rtol=1e-15, atol=0)
+    err = np.abs(_vec(f) - ref).max(axis=1) / ref_amag
     assert err.max() < 4e-16
+    assert (np.abs(f["phi"] - ref_phi) / ref_pmag).max() < 4e-16
 
 
 def test_force_is_minus_gradient_of_potential(orc):
