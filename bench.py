@@ -9,11 +9,20 @@ accumulation, FP64 push).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line:
   value      ordered pair interactions per second over the timed steps
-  roofline   the pair-sum kernel's achieved FP32 rate (20 flops per pair, the
-             usual count for a softened inverse-square interaction) over its
-             average duration, measured with HIP events on the stream it runs
-             on, against the 157.3 TFLOP/s FP32 vector peak of the MI355X (the
-             FP64 path: its FP64 rate against the 78.6 TFLOP/s FP64 peak)
+  roofline   the pair-sum kernel's achieved FP32 rate in algorithmic flops (20
+             per ordered pair, the usual count for a softened inverse-square
+             interaction) over its average duration, measured with HIP events
+             on the stream it runs on, against the 157.3 TFLOP/s FP32 vector
+             peak of the MI355X (the FP64 path: its FP64 rate against the 78.6
+             TFLOP/s FP64 peak).  The symmetric kernel evaluates each unordered
+             pair once for two ordered interactions (Newton's third law), so
+             its algorithmic rate counts work it did not have to issue; for it
+             the fraction of the FP32 vector peak the hardware actually
+             delivered is counted_frac: the FP32 flops rocprofv3 counted for
+             the same kernel, workload, tiling and sources
+             (SQ_INSTS_VALU_FLOPS_FP32, stored beside the profile under
+             profiles/), over the same measured duration.  counted_frac and
+             counted_tflops are null when no stored count matches.
   cpu_baseline  the CPU oracle on a bounded sample of the same field evaluation
 """
 from __future__ import annotations
@@ -33,15 +42,21 @@ PEAK_FP64_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "pair_sym_cold_sphere_1m_counters.json")
 
 
-def stored_counters(workload, kernel):
-    """Hardware-counter figures measured for this kernel and workload (see
-    profiles/), used only while the kernel sources still hash to the value
-    recorded with them."""
+TUNING_KEYS = ("symmetric", "i_per_lane", "far_split", "sym_split")
+
+
+def stored_counters(workload, kernel, tuning):
+    """Hardware-counter figures measured for this kernel, workload and tiling
+    (see profiles/), used only while the kernel sources still hash to the
+    value recorded with them."""
     import hashlib
     if not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
     if rec.get("workload") != workload or not rec.get("kernel", "").startswith(kernel):
+        return None
+    want = rec.get("tuning")
+    if not want or any(want.get(k) != tuning.get(k) for k in TUNING_KEYS):
         return None
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])).hexdigest()[:16]
     return rec if h == rec.get("source_sha256_16") else None
@@ -70,7 +85,8 @@ def parse():
                         "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases); "
                         "oracle: time only the CPU oracle on --cpu-threads threads (no GPU); tilings: pair-stage time of "
                         "the default tiling against the ordered kernel and the unsplit symmetric ones at --sizes")
-    p.add_argument("--paper-cases", default="main,dt,np", help="subset of main,dt,np for --mode paper")
+    p.add_argument("--paper-cases", default="main,dt,np,pic,long",
+                   help="subset of main,dt,np,pic,long for --mode paper")
     p.add_argument("--every", type=int, default=20)
     p.add_argument("--precisions", default="mixed,fp64")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -232,7 +248,8 @@ def run_series(sim, n_steps, every):
 
     def record():
         for k, d in enumerate(sim.diagnostics()):
-            series[k].append((d["time"], d["emittance"][0], d["x_rms"][0], d["total"]))
+            series[k].append((d["time"], d["emittance"][0], d["x_rms"][0], d["total"], d["x_max"][0],
+                              d["v_rms"][0], d["v_max"][0]))
 
     record()
     t_run, done = 0.0, 0
@@ -255,11 +272,42 @@ def paper_tuning(every):
     return {"graph_steps": max(1, min(200, every))}
 
 
+# The PP runs of the paper's PIC comparison: the 8^3 = 512-particle cube at
+# dt = 1e-12 s, 100 steps (Sec. 3.2) and to 3200 ps (Sec. 3.3), with the
+# paper's serial wall times (other hardware; context, not a target).
+PAPER_512 = {"pic": {"steps": 100, "every": 10, "paper_serial_s": 0.28},
+             "long": {"steps": 3200, "every": 100, "paper_serial_s": 23.0}}
+
+
+def cpu_baseline_vv(b, n_steps):
+    """The CPU oracle's Velocity Verlet run of one bunch (trajectory only, no
+    diagnostics), timed on one thread and on every host core."""
+    from oracle.oracle import OracleState, default
+    orc = default()
+    every_core = orc.num_threads()
+    out = {"kind": "oracle", "steps": n_steps, "n": b.n,
+           "pairs": float(b.n) * (b.n - 1) * (n_steps + 1)}
+    try:
+        for label, nt in (("serial", 1), ("all_cores", every_core)):
+            orc.set_num_threads(nt)
+            s = OracleState(b.x, b.y, b.z, b.vx, b.vy, b.vz, b.q, b.m, b.weight, b.softening, b.dt)
+            t0 = time.perf_counter()
+            orc.vv(s, n_steps)
+            out[f"{label}_s"] = time.perf_counter() - t0
+            out[f"{label}_cores"] = nt
+    finally:
+        orc.set_num_threads(every_core)
+    return out
+
+
 def paper(a):
-    """The paper's own PP runs (Sec. 2.2): the 16^3 cube lattice to 10 ns at
-    dt = 1e-13 s, the time-step sweep {1e-13 .. 1e-10} s and the macro-particle
-    sweep {4^3 .. 32^3} (one batch), with the emittance of Eq. (I) sampled
-    every 0.1 ns.  Prints one JSON line."""
+    """The paper's own PP runs: the 16^3 cube lattice to 10 ns at dt = 1e-13 s,
+    the time-step sweep {1e-13 .. 1e-10} s and the macro-particle sweep
+    {4^3 .. 32^3} (one batch) of Sec. 2.2, with the emittance of Eq. (I)
+    sampled every 0.1 ns; the 512-particle PP runs of the PIC comparison
+    (Sec. 3.2: 100 steps of 1 ps; Sec. 3.3: to 3200 ps) with the observables
+    Sec. 3.2 plots, in both precisions, beside the serial CPU oracle on the
+    same runs.  Prints one JSON line."""
     import numpy as np
     from paper_2502_10640_amd import workloads as wl
     from paper_2502_10640_amd.sim import Simulation
@@ -268,12 +316,13 @@ def paper(a):
     def summary(bunches, prec, dt, series, t_run, n_steps):
         pairs = float(sum(b.n * (b.n - 1) for b in bunches)) * n_steps
         res = {"precision": prec, "dt_s": dt, "steps": n_steps, "n_particles": [b.n for b in bunches],
-               "wall_s": t_run, "pairs_per_s": pairs / t_run, "emittance_x": [], "x_rms": []}
+               "wall_s": t_run, "pairs_per_s": pairs / t_run, "emittance_x": [], "x_rms": [], "x_max": [],
+               "v_rms": [], "v_max": []}
         for k in range(len(bunches)):
             ser = np.array(series[k])
             e0 = ser[0, 3]
-            res["emittance_x"].append([float(v) for v in ser[:, 1]])
-            res["x_rms"].append([float(v) for v in ser[:, 2]])
+            for col, key in ((1, "emittance_x"), (2, "x_rms"), (4, "x_max"), (5, "v_rms"), (6, "v_max")):
+                res[key].append([float(v) for v in ser[:, col]])
             res.setdefault("max_rel_energy_drift", []).append(float(np.max(np.abs(ser[:, 3] - e0)) / abs(e0)))
         return res
 
@@ -308,6 +357,19 @@ def paper(a):
         with Simulation(bunches, "mixed", tuning=paper_tuning(every)) as sim:
             t_run, ser = run_series(sim, n_steps, every)
         out["cases"]["np_batch"] = summary(bunches, "mixed", bunches[0].dt, ser, t_run, n_steps)
+    for case, spec in PAPER_512.items():
+        if case not in cases:
+            continue
+        b = wl.paper_cube(8, dt=1e-12)
+        for prec in ("mixed", "fp64"):
+            print(f"[paper] 8^3 at dt = 1e-12 s, {spec['steps']} steps, {prec}", file=sys.stderr, flush=True)
+            with Simulation([b], prec, tuning=paper_tuning(spec["every"])) as sim:
+                t_run, ser = run_series(sim, spec["steps"], spec["every"])
+            res = summary([b], prec, b.dt, ser, t_run, spec["steps"])
+            res["paper_serial_wall_s"] = spec["paper_serial_s"]
+            out["cases"][f"{case}_{prec}"] = res
+        print(f"[paper] 8^3, {spec['steps']} steps: CPU oracle", file=sys.stderr, flush=True)
+        out["cases"][f"{case}_oracle"] = cpu_baseline_vv(b, spec["steps"])
     print(json.dumps(out))
 
 
@@ -382,16 +444,21 @@ def main():
         achieved = FLOPS_PER_PAIR * pairs / eval_s / 1e12
         roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None,
+                    "frac_kind": ("algorithmic: 20 flops per ordered pair; the symmetric kernel evaluates each "
+                                  "unordered pair once for two ordered interactions" if sym else
+                                  "algorithmic: 20 flops per ordered pair"),
+                    "counted_frac": None, "counted_tflops": None, "counted_source": None,
                     "kernel": kernel, "kernel_ms_per_evaluation": eval_s * 1e3,
                     "launches_per_evaluation": prof["launches"] / prof["evaluations"],
                     "avg_launch_ms": prof["total_ms"] / prof["launches"],
-                    "flops_per_pair": FLOPS_PER_PAIR, "flop_count": "20 per ordered pair interaction"}
-        rec = stored_counters(a.workload, kernel) if not a.n else None
+                    "flops_per_pair": FLOPS_PER_PAIR}
+        rec = stored_counters(a.workload, kernel, used_tuning) if not a.n else None
         if rec:
             roofline["traffic"] = rec["traffic_bytes_per_evaluation"]
             counted = rec["counted_fp32_flops_per_evaluation"] / eval_s / 1e12
-            roofline["counted_fp32"] = {"achieved": counted, "frac": counted / PEAK_FP32_TFLOPS,
-                                        "source": os.path.relpath(COUNTERS, ROOT)}
+            roofline["counted_tflops"] = counted
+            roofline["counted_frac"] = counted / PEAK_FP32_TFLOPS
+            roofline["counted_source"] = os.path.relpath(COUNTERS, ROOT)
     sim.close()
     base = None
     if not a.no_cpu_baseline:
@@ -413,7 +480,8 @@ def main():
                    "pairs_per_step": pairs, "precision": a.precision,
                    "pair_math": "f32 hi/lo separations, two-sum tile accumulation" if a.precision == "mixed"
                    else "f64", "push": "f64 velocity Verlet", "graph": a.graph,
-                   "parallelism": "single GPU", "tuning": used_tuning},
+                   "parallelism": "single GPU",
+                   "tuning": ",".join(f"{k}={v}" for k, v in used_tuning.items())},
         "roofline": roofline,
         "cpu_baseline": base,
     }

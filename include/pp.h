@@ -31,6 +31,13 @@
  *   - Work is enqueued on the context's stream and is asynchronous unless a
  *     call says otherwise.  One context must not be used from two host threads
  *     at once.  Different contexts are independent.
+ *   - Failure testing: when the environment variable PP_FAULT_INJECT holds
+ *     "alloc:N" or "launch:N" (N >= 1; "alloc" and "launch" mean N = 1) at
+ *     pp_create, the N-th device allocation or kernel launch that context
+ *     makes (counting from pp_create's first) fails without reaching the
+ *     device, as an out-of-memory error or a launch failure.  The failing call
+ *     returns PP_ERR_OUT_OF_MEMORY or PP_ERR_DEVICE and the context is broken
+ *     as after a real failure.
  */
 #ifndef PP_MI355X_PP_H
 #define PP_MI355X_PP_H
@@ -41,7 +48,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 3
+#define PP_ABI_VERSION 4
 
 typedef struct pp_ctx pp_ctx; /* opaque; owns its device scratch */
 
@@ -158,9 +165,24 @@ typedef struct {
                             ignores it.                                         */
 } pp_tuning;
 
-/* Create a context over n_bunches bunches of a state of n_total particles.
+/* Create a context over n_bunches bunches of a state of n_total particles:
+ * the set-up of Sec. 2.1 (N_p macro-particles per bunch of one weight w, each
+ * with the real-particle charge q and mass m of Eqs. (C)-(F)), ready for the
+ * field sum of Eq. (B) and the Velocity Verlet steps of Eqs. (G)/(H).
  * Inspects q and m on the device (FP64 reductions) to validate them and to
  * pick per-bunch charge scaling; synchronises the stream once.
+ * PP_MIXED: each bunch's positions enter the FP32 pair arithmetic relative to
+ * a frame fixed here from the bunch's extent (origin at the midpoint, scale a
+ * power of two near the half-extent R; exact in FP64).  The hi/lo split keeps
+ * each coordinate to about 2^-48 of its size in that frame, so once a bunch's
+ * centre has moved a distance D from the origin a separation d carries an
+ * extra relative error of about 2^-48 (D + R) / |d|, beside the 2^-24 of the
+ * FP32 pair arithmetic: negligible while D is well below 2^24 |d| (for the
+ * closest pairs of a 10^6-particle sphere, about 10^3 - 10^4 R).  Before
+ * that, the near/far split of the symmetric schedule, whose threshold grows
+ * with the coordinates' size, finds fewer source groups far and the sum slows
+ * down.  pp_invalidate re-centres the frames; call it once a bunch has moved
+ * by more than a few R. 
  *   out         receives the context (host pointer, required)
  *   bunches     host array of n_bunches entries, read only during the call
  *   n_total     length of every state array; every bunch lies inside it
@@ -181,28 +203,36 @@ pp_status pp_create(pp_ctx **out, const pp_bunch *bunches, int32_t n_bunches, in
  * phi the self term j = i is excluded as in E.  Asynchronous. */
 pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi);
 
-/* Advance every bunch by n_steps >= 0 Velocity Verlet steps (Eqs. (G)/(H)),
- * each step a plain sequence of kernel launches.  The acceleration at the
+/* Advance every bunch by n_steps >= 0 Velocity Verlet steps (Sec. 2.1,
+ * Eqs. (G)/(H), with a = (q/m) E of Eqs. (D)/(F)), each step a plain sequence
+ * of kernel launches.  The acceleration at the
  * current positions is computed first if it is not known (first call, or after
  * pp_invalidate).  Asynchronous. */
 pp_status pp_push(pp_ctx *ctx, int64_t n_steps);
 
-/* Same trajectory as pp_push (bitwise, for the same tiling), driven by the
- * batched scheduler: one pair-sum stage per step serving every bunch from one
+/* Same trajectory as pp_push (bitwise, for the same tiling): Velocity Verlet
+ * steps of Sec. 2.1, Eqs. (G)/(H), of every bunch (the paper's weight and
+ * time-step sweeps of Sec. 2.2 as one batch), driven by the batched scheduler: one pair-sum stage per step serving every bunch from one
  * work list (or one round schedule); with PP_GRAPH the steps are replayed from hipGraphs
  * captured on first use; with PP_AUTOTUNE the tiling is chosen by timing
  * candidates once (the choice is kept in the context); PP_CHECK as above.
  * Asynchronous unless PP_AUTOTUNE runs a search or PP_CHECK is given. */
 pp_status pp_step_batched(pp_ctx *ctx, int64_t n_steps, uint32_t flags);
 
-/* Diagnostics of every bunch into out[0 .. n_bunches-1] (host memory).  Costs
- * one potential evaluation (O(N^2) per bunch) and FP64 reductions in a fixed
- * order; synchronises the stream. */
+/* Diagnostics of every bunch into out[0 .. n_bunches-1] (host memory): the
+ * beam quantities the paper follows (Sec. 2.2: the emittance of Eq. (I);
+ * Sec. 3.2: <x^2>^(1/2), x_max, <v_x^2>^(1/2), v_x,max), per axis, and the
+ * conserved quantities (total energy with the potential of Eq. (B)'s pair
+ * law, momentum, centre of mass).  Costs one potential evaluation (O(N^2) per
+ * bunch) and FP64 reductions in a fixed order; synchronises the stream. */
 pp_status pp_diagnostics(pp_ctx *ctx, pp_diag *out);
 
-/* Declare that the caller changed r or v (the cached acceleration and the
- * step counter's meaning are reset: a(t) is recomputed on the next push; the
- * far split's spatial order is recomputed at the next evaluation). */
+/* Declare that the caller changed r or v: a(t) is recomputed on the next
+ * push and the far split's spatial order at the next evaluation.  PP_MIXED:
+ * the frames of pp_create are re-centred on the current positions (a device
+ * reduction; synchronises the stream).  A non-finite position gives
+ * PP_ERR_NOT_FINITE and leaves the frames as they were (the context stays
+ * usable). */
 pp_status pp_invalidate(pp_ctx *ctx);
 
 /* Read or replace the tiling.  Setting checks ranges (PP_ERR_INVALID_ARG) and
@@ -234,6 +264,14 @@ pp_status pp_get_profile(pp_ctx *ctx, pp_profile *out);
 
 /* Synchronise the context stream. */
 pp_status pp_sync(pp_ctx *ctx);
+
+/* Device memory accounting: bytes of device memory ctx currently holds (its
+ * scratch: acceleration, source mirror, partial sums, work lists, sort
+ * buffers, diagnostics), or, for ctx = NULL, the total over every live context
+ * of the process.  After pp_destroy of every context the total is 0, also for
+ * contexts broken by a failure half-way through a call.  Host only; never
+ * fails. */
+int64_t pp_device_bytes(const pp_ctx *ctx);
 
 /* Release every resource of the context (synchronises first).  NULL is a
  * no-op.  Valid in every state; the context must not be used afterwards. */

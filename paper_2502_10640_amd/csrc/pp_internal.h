@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstdint>
 
 namespace ppk {
@@ -42,6 +43,102 @@ struct BunchDev {
   int32_t gbase;      // spatial sort: first 64-particle group box of the bunch
   int32_t bbase;      // symmetric schedule: first block of the bunch over all bunches
 };
+
+// Coulomb constant 1/(4 pi eps0) from the CODATA 2018 vacuum permittivity.
+inline double coulomb_k() { return 1.0 / (4.0 * 3.14159265358979323846 * 8.8541878128e-12); }
+
+// Set-up reductions over a bunch: min and max of x, y, z, q and m, the count
+// of non-finite values, padding (MM_* slots of one record).
+enum MinMaxSlot : int32_t { MM_X = 0, MM_Y = 2, MM_Z = 4, MM_Q = 6, MM_M = 8, MM_NONFIN = 10, MM_LEN = 12 };
+
+// 2^-ceil(log2 h) for h > 0, exactly: frexp gives h = f 2^e with f in [0.5, 1),
+// and ceil(log2 h) is e - 1 when f = 0.5 (h a power of two), else e.
+__host__ __device__ inline double frame_scale(double h) {
+  int e = 0;
+  const double f = frexp(h, &e);
+  return ldexp(1.0, f == 0.5 ? 1 - e : -e);
+}
+
+// Frame of the mixed path and the factors of the field and the potential of
+// one bunch from its set-up extents r[MM_LEN] (the same arithmetic on the host
+// and on the device): origin at the midpoint of the extent, scale
+// 2^-ceil(log2 half-extent) (at least the softening; exact), and, with
+// set_q, the reference charge (the charge of largest magnitude, 1 if all are
+// zero).  Returns whether the charges are all equal.
+__host__ __device__ inline bool frame_from_extents(const double* r, double weight, double softening, double kc,
+                                                   bool mixed, bool set_q, BunchDev& B) {
+#pragma clang fp contract(off)
+  double half = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    B.origin[a] = 0.5 * (r[2 * a] + r[2 * a + 1]);
+    half = fmax(half, 0.5 * (r[2 * a + 1] - r[2 * a]));
+  }
+  half = fmax(fmax(half, softening), 1e-300);
+  B.scale = frame_scale(half);
+  const double qlo = r[MM_Q], qhi = r[MM_Q + 1];
+  if (set_q) {
+    double qref = fabs(qhi) >= fabs(qlo) ? qhi : qlo;
+    if (qref == 0.0) qref = 1.0;
+    B.qref = qref;
+  }
+  const double qref = B.qref;
+  if (mixed) {
+    B.kE = kc * weight * qref * B.scale * B.scale;
+    B.kPhi = kc * weight * qref * B.scale;
+    const double es = softening * B.scale;
+    B.eps2s = (float)(es * es);
+  } else {
+    B.kE = kc * weight * qref;
+    B.kPhi = kc * weight * qref;
+    B.eps2 = softening * softening;
+  }
+  return qlo == qhi;
+}
+
+// Source chunks of one bunch of n particles in the ordered-pair work list
+// (receiver blocks of i_per_lane x WG): a bunch's sources are split into
+// chunks of about 2^chunk_pairs_log2 pair interactions, and into at least
+// enough chunks for the bunch alone to give cus x grid_per_cu items (down to
+// CHUNK_MIN-source chunks), with the fill alone capped at FILL_CHUNKS chunks
+// while that still leaves two items per CU.  Depends only on the bunch's own
+// size and the device, so a bunch gives the same bits alone or in a batch.
+constexpr int64_t FILL_CHUNKS = 32;
+
+struct Chunking {
+  int64_t n_chunks;
+  int64_t chunk_len;
+};
+
+inline Chunking ordered_chunking(int64_t n, int i_per_lane, int chunk_pairs_log2, int grid_per_cu, int cus) {
+  const int64_t BI = (int64_t)i_per_lane * WG;
+  const double full = (double)(n < BI ? n : BI) * (double)n;
+  const int64_t max_ch = (n + CHUNK_MIN - 1) / CHUNK_MIN;
+  const int64_t nib0 = (n + BI - 1) / BI;
+  const int64_t fill = (int64_t)cus * grid_per_cu;
+  // chunk length for a wanted chunk count, and the chunk count it gives;
+  // chunks are whole LDS tiles (JT sources) where that still fills the GPU,
+  // else multiples of CHUNK_MIN sources (a partly filled tile)
+  auto chunking = [&](int64_t want, int64_t* len) {
+    want = want < 1 ? 1 : (want > max_ch ? max_ch : want);
+    const int64_t per = (n + want - 1) / want;
+    const int64_t gran = per >= JT ? JT : CHUNK_MIN;
+    *len = ((per + gran - 1) / gran) * gran;
+    return (n + *len - 1) / *len;
+  };
+  const int64_t by_pairs = (int64_t)llround(full / ldexp(1.0, chunk_pairs_log2));
+  const int64_t by_fill = (fill + nib0 - 1) / nib0;
+  Chunking c{0, 0};
+  c.n_chunks = chunking(by_pairs > by_fill ? by_pairs : by_fill, &c.chunk_len);
+  if (by_fill > FILL_CHUNKS && by_pairs < FILL_CHUNKS) {
+    int64_t len = 0;
+    const int64_t capped = chunking(FILL_CHUNKS, &len);
+    if (capped == FILL_CHUNKS && capped * nib0 >= 2 * (int64_t)cus) {
+      c.n_chunks = capped;
+      c.chunk_len = len;
+    }
+  }
+  return c;
+}
 
 // One unit of pair work: receivers [i0, i0 + i_per_lane * WG) of bunch b
 // against the sources of chunk `chunk` of the same bunch.
@@ -166,6 +263,7 @@ struct PackArgs {
   const double *vx, *vy, *vz;
   const double *ax, *ay, *az;
   float *xh, *yh, *zh, *xl, *yl, *zl;
+  double *sx, *sy, *sz;    // FP64 source copy of the positions (fused FP64 schedule), or null
   int32_t* counter;
 };
 
@@ -191,10 +289,31 @@ struct FinalArgs {
   double *ex, *ey, *ez, *phi;   // FIN_FIELD outputs (phi may be null)
   int32_t sym;                  // partials are the symmetric accumulators
   const int32_t* rank;          // symmetric accumulators in sorted order: slot = rank[i]
-  // FIN_KICK_DRIFT: positions, mixed mirror and the pair kernel's work counter
+  // FIN_KICK_DRIFT: positions, mixed mirror (or FP64 source copy, where
+  // given) and the pair kernel's work counter
   double *x, *y, *z;
   float *xh, *yh, *zh, *xl, *yl, *zl;
+  double *sx, *sy, *sz;
   int32_t* counter;
+};
+
+// Fused small-bunch schedule (pp_fused.hip): one workgroup per item computes
+// the whole field of receivers [i0, i0 + R) of bunch b and applies the update.
+struct FusedItem {
+  int32_t b;
+  int32_t i0;
+};
+
+struct FusedArgs {
+  const BunchDev* bunches;
+  const FusedItem* items;
+  // this step's sources: mixed mirror planes (qt: normalised charge), or the
+  // FP64 source copy and the FP64 normalised charge
+  const float *xh, *yh, *zh, *xl, *yl, *zl, *qt;
+  const double *x, *y, *z, *qt64;
+  // the update (state, outputs; FIN_KICK_DRIFT: the next step's source
+  // buffer in xh..zl or sx..sz)
+  FinalArgs upd;
 };
 
 // Diagnostics: per-bunch reduction record in device memory (doubles).
@@ -231,6 +350,13 @@ struct DiagArgs {
 
 }  // namespace ppk
 
+// Message returned by pp_last_error(NULL) on the calling thread (set by the
+// calls that have no context).
+#include <string>
+namespace ppk {
+void set_thread_error(const std::string& msg);
+}  // namespace ppk
+
 // Launchers (pp_kernels.hip).  Each returns the hipGetLastError() status.
 namespace ppk {
 hipError_t launch_pack(const PackArgs& a, bool drift, bool mixed, hipStream_t s);
@@ -253,4 +379,9 @@ hipError_t launch_diag(const DiagArgs& a, int32_t n_bunches, hipStream_t s);
 hipError_t launch_fill_bid(int32_t* bid, int64_t n_total, const BunchDev* bunches, int32_t n_bunches,
                            hipStream_t s);
 int pair_regs_hint(bool mixed, int i_per_lane);
+// Fused small-bunch schedule: receivers per item, and the launch of one
+// evaluation (one workgroup per item).
+int fused_receivers_per_item(int i_per_lane, int lanes);
+hipError_t launch_fused(const FusedArgs& a, bool mixed, int i_per_lane, int lanes, FinalMode mode, bool uniform_q,
+                        bool with_phi, int n_items, hipStream_t s);
 }  // namespace ppk

@@ -20,6 +20,7 @@
 #include "pp_device.h"
 #include "pp_device64.h"
 #include "pp_internal.h"
+#include "pp_update.h"
 
 #include <cfloat>
 #include <cmath>
@@ -295,24 +296,6 @@ __global__ __launch_bounds__(WG) void pair_fp64_kernel(PairArgs a, int32_t sum_t
 // Drift (Eq. (G)) fused with the mixed-path source pack; also resets the
 // persistent work counter for the pair kernel that follows on the stream.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double drift1(double r, double v, double acc, double dt) {
-#pragma clang fp contract(off)
-  return r + v * dt + acc * dt * dt / 2.0;
-}
-
-// mirror of one particle: u = (r - origin) * scale, hi = fl32(u), lo = fl32(u - hi)
-__device__ __forceinline__ void mirror1(double ox, double oy, double oz, double scale, int64_t i, double x, double y,
-                                        double z, float* xh, float* yh, float* zh, float* xl, float* yl, float* zl) {
-  const double ux = (x - ox) * scale;
-  const double uy = (y - oy) * scale;
-  const double uz = (z - oz) * scale;
-  const float hx = (float)ux, hy = (float)uy, hz = (float)uz;
-  xh[i] = hx; yh[i] = hy; zh[i] = hz;
-  xl[i] = (float)(ux - (double)hx);
-  yl[i] = (float)(uy - (double)hy);
-  zl[i] = (float)(uz - (double)hz);
-}
-
 template <bool DRIFT, bool MIXED>
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,17 +315,13 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     a.x[i] = x; a.y[i] = y; a.z[i] = z;
   }
   if (MIXED) mirror1(ox, oy, oz, scale, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
+  else if (a.sx) { a.sx[i] = x; a.sy[i] = y; a.sz[i] = z; }
 }
 
 // ---------------------------------------------------------------------------
 // Chunk combine in FP64 + field output, acceleration (Eq. (D)/(F)) or kick
 // (Eq. (H)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double kick1(double v, double a0, double a1, double dt) {
-#pragma clang fp contract(off)
-  return v + (a0 + a1) * dt / 2.0;
-}
-
 // L lanes per particle.  The ordered-pair path uses L = FIN_LANES: lane t adds
 // chunks t, t + L, ... in order, then an xor butterfly over the L lanes (every
 // lane ends with the same bits, a + b == b + a); the rule depends only on the
@@ -410,46 +389,7 @@ __global__ __launch_bounds__(256) void final_kernel(FinalArgs a) {
     }
     if (t != 0) return;
   }
-  // Everything the update reads, loaded before its first store: read after
-  // them, the loads of x would wait for the stores of v and the bunch
-  // constants for the stores of x (the compiler cannot rule out aliasing),
-  // each a further round trip to memory.
-  const double dt = B.dt, kE = B.kE;
-  double ox = 0.0, oy = 0.0, oz = 0.0, scale = 0.0;
-  double qi = 0.0, mi = 1.0, v0x = 0.0, v0y = 0.0, v0z = 0.0, a0x = 0.0, a0y = 0.0, a0z = 0.0;
-  double rx = 0.0, ry = 0.0, rz = 0.0;
-  if (MODE != FIN_FIELD) { qi = a.q[i]; mi = a.m[i]; }
-  if (MODE == FIN_KICK || MODE == FIN_KICK_DRIFT) {
-    v0x = a.vx[i]; v0y = a.vy[i]; v0z = a.vz[i];
-    a0x = a.ax[i]; a0y = a.ay[i]; a0z = a.az[i];
-  }
-  if (MODE == FIN_KICK_DRIFT) {
-    rx = a.x[i]; ry = a.y[i]; rz = a.z[i];
-    if (MIXED) { ox = B.origin[0]; oy = B.origin[1]; oz = B.origin[2]; scale = B.scale; }
-  }
-  ex *= kE; ey *= kE; ez *= kE;
-  if (MODE == FIN_FIELD) {
-    if (a.ex) { a.ex[i] = ex; a.ey[i] = ey; a.ez[i] = ez; }
-    if (want_phi) a.phi[i] = ph * B.kPhi;
-    return;
-  }
-  const double qm = qi / mi;
-  const double nax = ex * qm, nay = ey * qm, naz = ez * qm;
-  if (MODE == FIN_KICK || MODE == FIN_KICK_DRIFT) {
-    const double vx = kick1(v0x, a0x, nax, dt);
-    const double vy = kick1(v0y, a0y, nay, dt);
-    const double vz = kick1(v0z, a0z, naz, dt);
-    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
-    if (MODE == FIN_KICK_DRIFT) {
-      // the next step's drift (Eq. (G)) with the velocity and acceleration just stored
-      const double x = drift1(rx, vx, nax, dt);
-      const double y = drift1(ry, vy, nay, dt);
-      const double z = drift1(rz, vz, naz, dt);
-      a.x[i] = x; a.y[i] = y; a.z[i] = z;
-      if (MIXED) mirror1(ox, oy, oz, scale, i, x, y, z, a.xh, a.yh, a.zh, a.xl, a.yl, a.zl);
-    }
-  }
-  a.ax[i] = nax; a.ay[i] = nay; a.az[i] = naz;
+  update_particle<MIXED, MODE>(a, B, i, ex, ey, ez, ph, want_phi);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,7 +421,7 @@ __global__ __launch_bounds__(256) void qprep_kernel(const BunchDev* bunches, con
 
 // Extents for set-up: per bunch [min x, max x, min y, max y, min z, max z,
 // min q, max q, min m, max m, non-finite count, 0].
-constexpr int MM = 12;
+constexpr int MM = MM_LEN;
 
 __device__ __forceinline__ bool fin(double v) { return isfinite(v); }
 

@@ -14,6 +14,7 @@
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cerrno>
 #include <cmath>
 #include <cstddef>
@@ -26,6 +27,7 @@
 #include <queue>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using ppk::BunchDev;
@@ -33,12 +35,17 @@ using ppk::WorkItem;
 
 namespace {
 
-// Coulomb constant from the CODATA 2018 vacuum permittivity.
-constexpr double kEps0 = 8.8541878128e-12;
-constexpr double kPi = 3.14159265358979323846;
-const double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
+const double kCoulomb = ppk::coulomb_k();
 
 thread_local std::string g_create_error;
+
+// Device bytes held by every context of the process (pp_device_bytes).
+std::atomic<int64_t> g_live_bytes{0};
+
+// Test hook: PP_FAULT_INJECT = "alloc:N" or "launch:N" (N >= 1, default 1),
+// read by pp_create, makes the N-th device allocation or kernel launch of that
+// context fail without calling HIP, as an out-of-memory or a launch failure.
+enum class Fault : int32_t { kNone = 0, kAlloc = 1, kLaunch = 2 };
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
@@ -121,6 +128,12 @@ struct pp_ctx {
   std::string err;
   bool broken = false;
 
+  std::unordered_map<void*, size_t> live;  // device allocations of this context and their sizes
+  int64_t live_bytes = 0;
+  Fault fault = Fault::kNone;              // injected fault (test hook) and the calls left before it
+  int64_t fault_left = 0;
+  double* mmbuf = nullptr;                 // set-up reductions (extents, charge range, mass check)
+
   float* xh() const { return mir; }
   float* plane(int k) const { return mir + (size_t)k * (size_t)n_total; }
   bool mixed() const { return prec == PP_MIXED; }
@@ -155,6 +168,74 @@ pp_status dev_fail(pp_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return dev_fail((c), e_, #call); \
   } while (0)
 
+// True when the injected fault of kind k fires now (once).
+bool fault_fires(pp_ctx* c, Fault k) {
+  if (c->fault != k) return false;
+  if (--c->fault_left > 0) return false;
+  c->fault = Fault::kNone;
+  return true;
+}
+
+void read_fault_hook(pp_ctx* c) {
+  const char* e = std::getenv("PP_FAULT_INJECT");
+  if (!e || !*e) return;
+  const std::string v(e);
+  const size_t colon = v.find(':');
+  const std::string kind = v.substr(0, colon);
+  long long n = 1;
+  if (colon != std::string::npos) n = std::atoll(v.c_str() + colon + 1);
+  if (n < 1) return;
+  if (kind == "alloc") c->fault = Fault::kAlloc;
+  else if (kind == "launch") c->fault = Fault::kLaunch;
+  else return;
+  c->fault_left = n;
+}
+
+// Every device allocation of a context: recorded (pp_device_bytes) and freed
+// through dfree.
+hipError_t dalloc_bytes(pp_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 1;
+  if (fault_fires(c, Fault::kAlloc)) return hipErrorOutOfMemory;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  c->live[*p] = bytes;
+  c->live_bytes += (int64_t)bytes;
+  g_live_bytes += (int64_t)bytes;
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t dalloc(pp_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  const hipError_t e = dalloc_bytes(c, &q, std::max<size_t>(count, 1) * sizeof(T));
+  *p = (T*)q;
+  return e;
+}
+
+hipError_t dfree(pp_ctx* c, void* p) {
+  if (!p) return hipSuccess;
+  const auto it = c->live.find(p);
+  if (it != c->live.end()) {
+    c->live_bytes -= (int64_t)it->second;
+    g_live_bytes -= (int64_t)it->second;
+    c->live.erase(it);
+  }
+  return hipFree(p);
+}
+
+// Every kernel launch of a context passes this gate first.
+hipError_t launch_gate(pp_ctx* c) { return fault_fires(c, Fault::kLaunch) ? hipErrorLaunchFailure : hipSuccess; }
+
+#define PP_LAUNCH(c, call)          \
+  do {                              \
+    PP_HIP((c), launch_gate(c));    \
+    PP_HIP((c), (call));            \
+  } while (0)
+
 // Frees a context-owned device buffer before it is reallocated (callers have
 // synchronised the stream, so nothing of it is in flight); a failure is a
 // device error of the context.
@@ -163,7 +244,7 @@ pp_status release(pp_ctx* c, T*& p) {
   if (!p) return PP_OK;
   void* q = p;
   p = nullptr;
-  PP_HIP(c, hipFree(q));
+  PP_HIP(c, dfree(c, q));
   return PP_OK;
 }
 
@@ -174,13 +255,6 @@ pp_status usable(pp_ctx* c) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-template <class T>
-hipError_t dalloc(T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc((void**)p, count * sizeof(T));
-}
 
 // Host <-> device copies go through a pinned staging buffer owned by the
 // context, enqueued on the context stream and waited for before returning:
@@ -297,56 +371,48 @@ pp_status build_sym(pp_ctx* c) {
   if (slot_need > c->slot_bytes) {
     c->slot_bytes = 0;
     if ((st = release(c, c->slot)) != PP_OK) return st;
-    PP_HIP(c, hipMalloc(&c->slot, slot_need));
+    PP_HIP(c, dalloc_bytes(c, &c->slot, slot_need));
     c->slot_bytes = slot_need;
   }
   if (items.size() > c->sitems_cap) {
     c->sitems_cap = 0;
     if ((st = release(c, c->sitems)) != PP_OK) return st;
-    PP_HIP(c, dalloc(&c->sitems, items.size()));
+    PP_HIP(c, dalloc(c, &c->sitems, items.size()));
     c->sitems_cap = items.size();
   }
-  if (!c->acc) PP_HIP(c, hipMalloc(&c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total * c->acc_elem()));
+  if (!c->acc) PP_HIP(c, dalloc_bytes(c, &c->acc, (size_t)ppk::SYM_PLANES * (size_t)c->n_total * c->acc_elem()));
   if (c->far() && !c->smir) {
     // host-side shape checks of what the sort kernels assume
     if (c->n_total > INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "far split: more than 2^31 - 1 particles");
     const size_t n = (size_t)c->n_total, nin = (size_t)c->n_in;
     const size_t tiles = (nin + ppk::SORT_TILE - 1) / ppk::SORT_TILE;
-    PP_HIP(c, dalloc(&c->smir, 7 * n));
-    PP_HIP(c, dalloc(&c->keys, 2 * nin));
-    PP_HIP(c, dalloc(&c->vals, 2 * nin));
-    PP_HIP(c, dalloc(&c->hist, 256 * (tiles + 1)));  // + 256 digit totals
-    PP_HIP(c, dalloc(&c->rank, n));
-    PP_HIP(c, dalloc(&c->ubits, (size_t)c->nb));
-    PP_HIP(c, dalloc(&c->gbox, (size_t)ppk::GBOX * (size_t)c->n_groups));
+    PP_HIP(c, dalloc(c, &c->smir, 7 * n));
+    PP_HIP(c, dalloc(c, &c->keys, 2 * nin));
+    PP_HIP(c, dalloc(c, &c->vals, 2 * nin));
+    PP_HIP(c, dalloc(c, &c->hist, 256 * (tiles + 1)));  // + 256 digit totals
+    PP_HIP(c, dalloc(c, &c->rank, n));
+    PP_HIP(c, dalloc(c, &c->ubits, (size_t)c->nb));
+    PP_HIP(c, dalloc(c, &c->gbox, (size_t)ppk::GBOX * (size_t)c->n_groups));
   }
   return h2d(c, c->sitems, items.data(), items.size() * sizeof(ppk::SymItem));
 }
 
 // ---------------------------------------------------------------------------
-// Work list: items (bunch, j-chunk, first receiver), heaviest first.
+// Work list: items (bunch, j-chunk, first receiver), heaviest first.  The
+// chunking rule is ppk::ordered_chunking.  Its fill cap (FILL_CHUNKS):
+// measured at 4096 particles (16^3 cube, hipGraph replay), 32 chunks were
+// 11-13% faster per step than 64 in both precisions.  Where rounding the chunk
+// length up to 64 sources leaves fewer chunks the cap did not pay (3000
+// particles: 24 chunks, one item per CU, 5% slower; 5000: 27 chunks, FP64 7%
+// slower), so it applies only when exactly 32 chunks remain; at 2048, 8192 and
+// 16384 particles the rule gives 32 or fewer anyway.
 // ---------------------------------------------------------------------------
-// Most chunks the fill rule alone may split a bunch into (4 per lane of the
-// kick's 8-lane chunk sum), when that still leaves two items per CU.
-// Measured at 4096 particles (16^3 cube, hipGraph replay): 32 chunks 11-13%
-// faster per step than 64 in both precisions.  Where rounding the chunk length
-// up to 64 sources leaves fewer chunks the cap did not pay (3000 particles:
-// 24 chunks, one item per CU, 5% slower; 5000: 27 chunks, FP64 7% slower), so
-// it applies only when exactly 32 chunks remain; at 2048, 8192 and 16384
-// particles the rule gives 32 or fewer anyway.
-constexpr int64_t kFillChunks = 32;
-
 pp_status build_items(pp_ctx* c) {
   pp_status st;
   // kernels still in flight may read the old list and partial planes
   PP_HIP(c, hipStreamSynchronize(c->stream));
   const int K = c->k_eff();
   const int64_t BI = (int64_t)K * ppk::WG;
-  const double wstar = std::ldexp(1.0, c->tun.chunk_pairs_log2);
-  // a bunch is split finely enough to fill the GPU on its own (the rule uses
-  // only the bunch's size and the device, so a bunch gives the same bits
-  // alone or inside a batch)
-  const int64_t fill = (int64_t)c->cus * c->tun.grid_per_cu;
 
   struct Cand { WorkItem w; double cost; };
   std::vector<Cand> cand;
@@ -354,35 +420,8 @@ pp_status build_items(pp_ctx* c) {
   int64_t cbase = 0, gbase = 0, bbase = 0;
   for (int b = 0; b < c->nb; ++b) {
     const int64_t n = c->hb[b].n;
-    const double full = (double)std::min(BI, n) * (double)n;
-    // chunks are whole LDS tiles (JT sources) where that still fills the GPU,
-    // else multiples of CHUNK_MIN sources (a partly filled tile)
-    const int64_t max_ch = (n + ppk::CHUNK_MIN - 1) / ppk::CHUNK_MIN;
-    const int64_t nib0 = (n + BI - 1) / BI;
-    // chunk length for a wanted chunk count, and the chunk count it gives
-    auto chunking = [&](int64_t want, int64_t* len) {
-      want = std::max<int64_t>(1, std::min(want, max_ch));
-      const int64_t per = (n + want - 1) / want;
-      const int64_t gran = per >= ppk::JT ? ppk::JT : ppk::CHUNK_MIN;
-      *len = ((per + gran - 1) / gran) * gran;
-      return (n + *len - 1) / *len;
-    };
-    const int64_t by_pairs = (int64_t)std::llround(full / wstar);
-    const int64_t by_fill = (fill + nib0 - 1) / nib0;
-    int64_t chunk_len = 0;
-    int64_t nch = chunking(std::max(by_pairs, by_fill), &chunk_len);
-    // the fill alone splits a bunch into at most kFillChunks chunks, as long
-    // as that still leaves two items per CU and the rounding of the chunk
-    // length keeps exactly kFillChunks chunks: beyond it the kick's chunk sums
-    // cost more than the extra items gain
-    if (by_fill > kFillChunks && by_pairs < kFillChunks) {
-      int64_t len = 0;
-      const int64_t capped = chunking(kFillChunks, &len);
-      if (capped == kFillChunks && capped * nib0 >= 2 * (int64_t)c->cus) {
-        nch = capped;
-        chunk_len = len;
-      }
-    }
+    const ppk::Chunking ch0 = ppk::ordered_chunking(n, K, c->tun.chunk_pairs_log2, c->tun.grid_per_cu, c->cus);
+    const int64_t nch = ch0.n_chunks, chunk_len = ch0.chunk_len;
     BunchDev& B = c->hbd[b];
     B.n_chunks = (int32_t)nch;
     B.chunk_len = chunk_len;
@@ -425,14 +464,14 @@ pp_status build_items(pp_ctx* c) {
   if (need > c->part_bytes) {
     c->part_bytes = 0;
     if ((st = release(c, c->part)) != PP_OK) return st;
-    PP_HIP(c, hipMalloc(&c->part, need));
+    PP_HIP(c, dalloc_bytes(c, &c->part, need));
     c->part_bytes = need;
   }
   c->P = pbase;
   if (items.size() > c->items_cap) {
     c->items_cap = 0;
     if ((st = release(c, c->items)) != PP_OK) return st;
-    PP_HIP(c, dalloc(&c->items, items.size()));
+    PP_HIP(c, dalloc(c, &c->items, items.size()));
     c->items_cap = items.size();
   }
   pp_status s;
@@ -528,7 +567,7 @@ hipEvent_t take_event(pp_ctx* c) {
 
 // The three launches of one evaluation, on stream s.
 pp_status enqueue_pack(pp_ctx* c, bool drift, hipStream_t s) {
-  PP_HIP(c, ppk::launch_pack(pack_args(c), drift, c->mixed(), s));
+  PP_LAUNCH(c, ppk::launch_pack(pack_args(c), drift, c->mixed(), s));
   return PP_OK;
 }
 
@@ -581,11 +620,11 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
-      PP_HIP(c, ppk::launch_sym64(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
+      PP_LAUNCH(c, ppk::launch_sym64(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
       if ((st = mark(c, timed, false, s)) != PP_OK) return st;
       fa.r0 = B.r0;
       fa.r1 = B.r1;
-      PP_HIP(c, ppk::launch_sym64_fold(fa, phi, s));
+      PP_LAUNCH(c, ppk::launch_sym64_fold(fa, phi, s));
     }
   } else if (c->sym()) {
     ppk::SymArgs sa{};
@@ -624,7 +663,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
       so.gbox = c->gbox;
       const bool resort = !perm_reusable(c, k);
       if (resort) c->perm_k = k;
-      PP_HIP(c, ppk::launch_sort_bits(so, c->key_shift, c->key_bits, c->n_groups, resort, s));
+      PP_LAUNCH(c, ppk::launch_sort_bits(so, c->key_shift, c->key_bits, c->n_groups, resort, s));
       sa.xh = sp[0]; sa.yh = sp[1]; sa.zh = sp[2];
       sa.xl = sp[3]; sa.yl = sp[4]; sa.zl = sp[5];
       sa.qt = sp[6];
@@ -644,16 +683,16 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
-      PP_HIP(c, ppk::launch_sym(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
+      PP_LAUNCH(c, ppk::launch_sym(sa, B.first, B.count, c->tun.i_per_lane, c->uniform_q, phi, s));
       if ((st = mark(c, timed, false, s)) != PP_OK) return st;
       fa.r0 = B.r0;
       fa.r1 = B.r1;
-      PP_HIP(c, ppk::launch_sym_fold(fa, phi, s));
+      PP_LAUNCH(c, ppk::launch_sym_fold(fa, phi, s));
     }
   } else {
     if ((st = mark(c, timed, true, s)) != PP_OK) return st;
-    PP_HIP(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
-                               grid_size(c), s));
+    PP_LAUNCH(c, ppk::launch_pair(pair_args(c), c->mixed(), c->k_eff(), c->tun.sum_tile, c->uniform_q, phi,
+                                  grid_size(c), s));
     if ((st = mark(c, timed, false, s)) != PP_OK) return st;
   }
   return PP_OK;
@@ -663,7 +702,7 @@ pp_status enqueue_final(pp_ctx* c, ppk::FinalMode mode, double* ex, double* ey, 
                         hipStream_t s) {
   ppk::FinalArgs a = final_args(c);
   a.ex = ex; a.ey = ey; a.ez = ez; a.phi = phi;
-  PP_HIP(c, ppk::launch_final(a, c->mixed(), mode, s));
+  PP_LAUNCH(c, ppk::launch_final(a, c->mixed(), mode, s));
   return PP_OK;
 }
 
@@ -732,7 +771,7 @@ pp_status capture_graph(pp_ctx* c, int64_t steps) {
 
 pp_status check_finite(pp_ctx* c) {
   PP_HIP(c, hipMemsetAsync(c->counter + 1, 0, sizeof(int32_t), c->stream));
-  PP_HIP(c, ppk::launch_check_finite(c->bid, c->n_total, c->arrptr, 9, c->counter + 1, c->stream));
+  PP_LAUNCH(c, ppk::launch_check_finite(c->bid, c->n_total, c->arrptr, 9, c->counter + 1, c->stream));
   int32_t flag = 0;
   pp_status s = d2h(c, &flag, c->counter + 1, sizeof(int32_t));
   if (s != PP_OK) return s;
@@ -989,7 +1028,7 @@ pp_status autotune(pp_ctx* c) {
     return apply_tuning(c, cached);
   }
   const size_t n3 = (size_t)c->n_total * 3;
-  if (!c->cmp_buf) PP_HIP(c, dalloc(&c->cmp_buf, 2 * n3));
+  if (!c->cmp_buf) PP_HIP(c, dalloc(c, &c->cmp_buf, 2 * n3));
   double* ref = c->cmp_buf;
   double* got = c->cmp_buf + n3;
   pp_status s;
@@ -1050,12 +1089,51 @@ pp_status autotune(pp_ctx* c) {
   return PP_OK;
 }
 
+// Set-up reductions over every bunch (per bunch: min and max of x, y, z, q
+// and m, and the count of non-finite values), then the per-bunch constants.
+constexpr int kMM = ppk::MM_LEN;
+constexpr int kMMG = 64;
+
+// Frame of the mixed path (origin at the midpoint of the bunch's extent, scale
+// the power of two 2^-ceil(log2 half-extent), exact), the charge scaling and
+// the field and potential factors.  At create it also validates q and m and
+// picks the reference charge; later (pp_invalidate) it only re-centres the
+// mixed path on the current positions, and a non-finite position leaves the
+// frames unchanged (PP_ERR_NOT_FINITE).
+pp_status setup_frames(pp_ctx* c, bool at_create) {
+  PP_HIP(c, launch_gate(c));
+  PP_HIP(c, ppk::launch_minmax(c->dbunch, c->nb, c->st.x, c->st.y, c->st.z, c->st.q, c->st.m, c->mmbuf, kMMG,
+                               c->stream));
+  std::vector<double> ext((size_t)c->nb * kMM);
+  pp_status st = d2h(c, ext.data(), c->mmbuf, ext.size() * sizeof(double));  // waits for the reduction
+  if (st != PP_OK) return st;
+  std::vector<BunchDev> hbd = c->hbd;
+  bool uniform = true;
+  for (int b = 0; b < c->nb; ++b) {
+    const double* r = &ext[(size_t)b * kMM];
+    char buf[160];
+    if (r[ppk::MM_NONFIN] != 0.0) {
+      std::snprintf(buf, sizeof buf, "bunch %d: %.0f particles with non-finite r, q or m", b, r[ppk::MM_NONFIN]);
+      return set_err(c, at_create ? PP_ERR_INVALID_ARG : PP_ERR_NOT_FINITE, buf);
+    }
+    if (at_create && !(r[ppk::MM_M] > 0.0)) {
+      std::snprintf(buf, sizeof buf, "bunch %d: mass must be > 0", b);
+      return set_err(c, PP_ERR_INVALID_ARG, buf);
+    }
+    const bool same_q =
+        ppk::frame_from_extents(r, c->hb[b].weight, c->hb[b].softening, kCoulomb, c->mixed(), at_create, hbd[b]);
+    if (!same_q) uniform = false;
+  }
+  if (at_create) c->uniform_q = uniform;
+  c->hbd = hbd;
+  return h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev));
+}
+
 void free_all(pp_ctx* c) {
   drop_graph(c);
-  auto f = [](void* p) { if (p) (void)hipFree(p); };
-  f(c->dbunch); f(c->bid); f(c->ax); f(c->ay); f(c->az); f(c->mir); f(c->qt64); f(c->part);
-  f(c->items); f(c->sitems); f(c->acc); f(c->slot);
-  f(c->smir); f(c->keys); f(c->vals); f(c->hist); f(c->rank); f(c->ubits); f(c->gbox); f(c->counter); f(c->phi); f(c->dweight); f(c->diag_buf); f(c->arrptr); f(c->cmp_buf);
+  // every device allocation the context still holds (the buffers above and
+  // any other), so that a context broken half-way through a call frees all
+  while (!c->live.empty()) (void)dfree(c, c->live.begin()->first);
   if (c->hpin) (void)hipHostFree(c->hpin);
   for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& p : c->ev_used) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
@@ -1063,6 +1141,10 @@ void free_all(pp_ctx* c) {
 }
 
 }  // namespace
+
+namespace ppk {
+void set_thread_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace ppk
 
 // ===========================================================================
 // C ABI
@@ -1106,6 +1188,7 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
 
   pp_ctx* c = new (std::nothrow) pp_ctx();
   if (!c) return set_err(nullptr, PP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  read_fault_hook(c);
   c->prec = prec;
   c->nb = n_bunches;
   c->n_total = n_total;
@@ -1132,16 +1215,16 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
   PP_CREATE_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
 
   const size_t n = (size_t)n_total;
-  PP_CREATE_HIP(dalloc(&c->dbunch, (size_t)n_bunches));
-  PP_CREATE_HIP(dalloc(&c->dweight, (size_t)n_bunches));
-  PP_CREATE_HIP(dalloc(&c->bid, n));
-  PP_CREATE_HIP(dalloc(&c->ax, n));
-  PP_CREATE_HIP(dalloc(&c->ay, n));
-  PP_CREATE_HIP(dalloc(&c->az, n));
-  PP_CREATE_HIP(dalloc(&c->counter, 4));
-  PP_CREATE_HIP(dalloc(&c->arrptr, 9));
-  if (prec == PP_MIXED) PP_CREATE_HIP(dalloc(&c->mir, 7 * n));
-  else PP_CREATE_HIP(dalloc(&c->qt64, n));
+  PP_CREATE_HIP(dalloc(c, &c->dbunch, (size_t)n_bunches));
+  PP_CREATE_HIP(dalloc(c, &c->dweight, (size_t)n_bunches));
+  PP_CREATE_HIP(dalloc(c, &c->bid, n));
+  PP_CREATE_HIP(dalloc(c, &c->ax, n));
+  PP_CREATE_HIP(dalloc(c, &c->ay, n));
+  PP_CREATE_HIP(dalloc(c, &c->az, n));
+  PP_CREATE_HIP(dalloc(c, &c->counter, 4));
+  PP_CREATE_HIP(dalloc(c, &c->arrptr, 9));
+  if (prec == PP_MIXED) PP_CREATE_HIP(dalloc(c, &c->mir, 7 * n));
+  else PP_CREATE_HIP(dalloc(c, &c->qt64, n));
 
   for (int b = 0; b < n_bunches; ++b) {
     BunchDev& B = c->hbd[b];
@@ -1162,69 +1245,17 @@ pp_status pp_create(pp_ctx** out, const pp_bunch* bunches, int32_t n_bunches, in
   PP_CREATE_HIP(hipMemsetAsync(c->ay, 0, n * sizeof(double), c->stream));
   PP_CREATE_HIP(hipMemsetAsync(c->az, 0, n * sizeof(double), c->stream));
   PP_CREATE_HIP(hipMemsetAsync(c->counter, 0, 4 * sizeof(int32_t), c->stream));
+  PP_CREATE_HIP(launch_gate(c));
   PP_CREATE_HIP(ppk::launch_fill_bid(c->bid, n_total, c->dbunch, n_bunches, c->stream));
   const double* tbl[9] = {S.x, S.y, S.z, S.vx, S.vy, S.vz, c->ax, c->ay, c->az};
   if ((st0 = h2d(c, c->arrptr, tbl, sizeof tbl)) != PP_OK) return fail(st0);
 
-  // device reductions over the bunches: extents, charge range, mass check
-  const int G = 64;
-  const int MM = 12;
-  double* mm = nullptr;
-  PP_CREATE_HIP(dalloc(&mm, (size_t)n_bunches * MM * (G + 1)));
-  hipError_t e = ppk::launch_minmax(c->dbunch, n_bunches, S.x, S.y, S.z, S.q, S.m, mm, G, c->stream);
-  std::vector<double> ext((size_t)n_bunches * MM);
-  if (e != hipSuccess) {
-    (void)hipFree(mm);  // the set-up already failed
-    return fail(dev_fail(c, e, "set-up reduction"));
-  }
-  st0 = d2h(c, ext.data(), mm, ext.size() * sizeof(double));  // waits for the reduction
-  if (st0 == PP_OK) st0 = release(c, mm);
-  else (void)hipFree(mm);
-  if (st0 != PP_OK) return fail(st0);
-
-  bool uniform = true;
-  for (int b = 0; b < n_bunches; ++b) {
-    const double* r = &ext[(size_t)b * MM];
-    char buf[160];
-    if (r[10] != 0.0) {
-      std::snprintf(buf, sizeof buf, "bunch %d: %.0f particles with non-finite r, q or m", b, r[10]);
-      c->err = buf;
-      return fail(PP_ERR_INVALID_ARG);
-    }
-    if (!(r[8] > 0.0)) {
-      std::snprintf(buf, sizeof buf, "bunch %d: mass must be > 0", b);
-      c->err = buf;
-      return fail(PP_ERR_INVALID_ARG);
-    }
-    BunchDev& B = c->hbd[b];
-    double half = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      B.origin[a] = 0.5 * (r[2 * a] + r[2 * a + 1]);
-      half = std::max(half, 0.5 * (r[2 * a + 1] - r[2 * a]));
-    }
-    half = std::max({half, bunches[b].softening, 1e-300});
-    const int ex2 = (int)std::ceil(std::log2(half));
-    B.scale = std::ldexp(1.0, -ex2);
-    const double qlo = r[6], qhi = r[7];
-    double qref = std::fabs(qhi) >= std::fabs(qlo) ? qhi : qlo;
-    if (qref == 0.0) qref = 1.0;
-    B.qref = qref;
-    if (qlo != qhi) uniform = false;
-    const double w = bunches[b].weight, eps = bunches[b].softening;
-    if (prec == PP_MIXED) {
-      B.kE = kCoulomb * w * qref * B.scale * B.scale;
-      B.kPhi = kCoulomb * w * qref * B.scale;
-      const double es = eps * B.scale;
-      B.eps2s = (float)(es * es);
-    } else {
-      B.kE = kCoulomb * w * qref;
-      B.kPhi = kCoulomb * w * qref;
-      B.eps2 = eps * eps;
-    }
-    c->pairs += (double)B.n * (double)(B.n - 1);
-  }
-  c->uniform_q = uniform;
-  if ((st0 = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return fail(st0);
+  // device reductions over the bunches: extents, charge range, mass check;
+  // the per-bunch constants (frame of the mixed path, charge scaling)
+  PP_CREATE_HIP(dalloc(c, &c->mmbuf, (size_t)n_bunches * kMM * (kMMG + 1)));
+  if ((st0 = setup_frames(c, true)) != PP_OK) return fail(st0);
+  for (int b = 0; b < n_bunches; ++b) c->pairs += (double)c->hbd[b].n * (double)(c->hbd[b].n - 1);
+  PP_CREATE_HIP(launch_gate(c));
   PP_CREATE_HIP(ppk::launch_qprep(c->dbunch, c->bid, n_total, S.q, c->mixed() ? c->plane(6) : nullptr, c->qt64,
                                   c->stream));
   c->tun = default_tuning(c->mixed(), c->hb, c->cus);
@@ -1278,7 +1309,7 @@ pp_status pp_step_batched(pp_ctx* c, int64_t n_steps, uint32_t flags) {
           (c->far() && c->graph.phase != c->step % kResortEvery)) {
         if ((s = capture_graph(c, c->tun.graph_steps)) != PP_OK) return s;
       }
-      PP_HIP(c, hipGraphLaunch(c->graph.exec, c->stream));
+      PP_LAUNCH(c, hipGraphLaunch(c->graph.exec, c->stream));
       if (c->far()) c->perm_k = c->step + c->graph.perm_offset;
       left -= c->graph.steps;
       c->step += c->graph.steps;
@@ -1295,12 +1326,12 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
   if ((s = usable(c)) != PP_OK) return s;
   if (!out) return set_err(c, PP_ERR_INVALID_ARG, "out is NULL");
   const int G = (int)std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / c->nb));
-  if (!c->phi) PP_HIP(c, dalloc(&c->phi, (size_t)c->n_total));
+  if (!c->phi) PP_HIP(c, dalloc(c, &c->phi, (size_t)c->n_total));
   const size_t need = (size_t)c->nb * ((size_t)G * ppk::D_N1 + ppk::D_NREC + ppk::D_OUT);
   if (need > c->diag_doubles) {
     c->diag_doubles = 0;
     if ((s = release(c, c->diag_buf)) != PP_OK) return s;  // the last diagnostics call synchronised
-    PP_HIP(c, dalloc(&c->diag_buf, need));
+    PP_HIP(c, dalloc(c, &c->diag_buf, need));
     c->diag_doubles = need;
   }
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
@@ -1315,7 +1346,7 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
   d.part = c->diag_buf + (size_t)c->nb * (ppk::D_NREC + ppk::D_OUT);
   d.rec = c->diag_buf;
   d.G = G;
-  PP_HIP(c, ppk::launch_diag(d, c->nb, c->stream));
+  PP_LAUNCH(c, ppk::launch_diag(d, c->nb, c->stream));
   std::vector<double> res((size_t)c->nb * ppk::D_OUT);
   if ((s = d2h(c, res.data(), c->diag_buf + (size_t)c->nb * ppk::D_NREC, res.size() * sizeof(double))) != PP_OK)
     return s;
@@ -1338,6 +1369,9 @@ pp_status pp_invalidate(pp_ctx* c) {
   if ((s = usable(c)) != PP_OK) return s;
   c->a_valid = false;
   c->perm_k = -1;
+  // re-centre the mixed path's frames on the current positions (the FP64 path
+  // uses positions as they are)
+  if (c->mixed()) return setup_frames(c, false);
   return PP_OK;
 }
 
@@ -1392,6 +1426,8 @@ pp_status pp_get_profile(pp_ctx* c, pp_profile* out) {
   c->prof_evals = 0;
   return PP_OK;
 }
+
+int64_t pp_device_bytes(const pp_ctx* c) { return c ? c->live_bytes : g_live_bytes.load(); }
 
 pp_status pp_sync(pp_ctx* c) {
   pp_status s;

@@ -17,8 +17,11 @@
 // partials are then added in wave order with two-sum and stored as the
 // source-side partial (S, C) of the item.  The receiver side is a plain FP32
 // sum over each group of 64 sources, two-summed into registers, and stored as
-// the receiver-side partial at the end of the item.  Both sides' plain sums
-// thus have the same worst-case bound, 63 u of their terms' magnitudes.
+// the receiver-side partial at the end of the item.  Worst-case bounds of the
+// plain sums: 63 u of the terms' magnitudes on the receiver side (64 terms),
+// (64 K - 1) u on the source side (64 K terms: 255 u at K = 4); errors of
+// random sign grow as the square root of the count (measured at most 6e-7 of
+// the terms' magnitude sum).
 //
 // Diagonal items (I == J, round 0) evaluate the ordered pairs inside one block
 // with the self term masked and have a receiver-side partial only.  Every

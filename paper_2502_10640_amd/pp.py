@@ -32,7 +32,7 @@ PP_CHECK = 4
 
 EXPORTS = ("pp_create", "pp_field", "pp_push", "pp_step_batched", "pp_diagnostics", "pp_invalidate",
            "pp_get_tuning", "pp_set_tuning", "pp_time_field", "pp_set_profiling", "pp_get_profile",
-           "pp_sync", "pp_destroy", "pp_last_error", "pp_abi_version")
+           "pp_sync", "pp_device_bytes", "pp_destroy", "pp_last_error", "pp_abi_version")
 
 
 class PPError(RuntimeError):
@@ -85,7 +85,7 @@ class Profile(ctypes.Structure):
 
 _LIB = None
 _VP = ctypes.c_void_p
-ABI_VERSION = 3  # PP_ABI_VERSION of include/pp.h
+ABI_VERSION = 4  # PP_ABI_VERSION of include/pp.h
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pp_set_profiling": ([_VP, ctypes.c_int32], st),
         "pp_get_profile": ([_VP, ctypes.POINTER(Profile)], st),
         "pp_sync": ([_VP], st),
+        "pp_device_bytes": ([_VP], ctypes.c_int64),
         "pp_destroy": ([_VP], st),
         "pp_last_error": ([_VP], ctypes.c_char_p),
         "pp_abi_version": ([], ctypes.c_int32),
@@ -208,6 +209,11 @@ def pp_get_profile(ctx) -> dict:
 
 def pp_sync(ctx) -> None:
     _check(load().pp_sync(ctx), ctx)
+
+
+def pp_device_bytes(ctx=None) -> int:
+    """Device bytes held by ctx, or by every live context when ctx is None."""
+    return int(load().pp_device_bytes(ctx))
 
 
 def pp_destroy(ctx) -> None:

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert pp.pp_abi_version() == 3
+    assert pp.pp_abi_version() == 4
 
 
 def test_destroy_null_and_last_error(lib):
@@ -82,3 +82,4 @@ def test_package_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import\s+oracle|from\s+oracle|libpporacle|pp_oracle|oracle_\w+\()", txt), f
+
