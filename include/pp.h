@@ -203,6 +203,35 @@ pp_status pp_create(pp_ctx **out, const pp_bunch *bunches, int32_t n_bunches, in
  * phi the self term j = i is excluded as in E.  Asynchronous. */
 pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi);
 
+/* Allocation-free field of one bunch, without a context.  For callers that
+ * cannot allocate device memory: code under hipGraph stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It calls no hipMalloc,
+ * hipFree or other allocating routine and reads nothing back to the host;
+ * every buffer it needs (bunch constants, work list, source mirror, partial
+ * sums) lies in one static device array of PP_NOALLOC_SCRATCH_MIB MiB per
+ * device, held from the first call on a device until the process ends.
+ *   n           particles, 1 <= n <= PP_NOALLOC_MAX_N (more: PP_ERR_INVALID_ARG)
+ *   x, y, z, q  device arrays of length n, FP64: positions [m] and
+ *               real-particle charges [C]; read only, not inspected on the host
+ *               (a non-finite value gives non-finite results)
+ *   weight, softening, prec   as for a pp_bunch / pp_create
+ *   ex, ey, ez  device outputs of length n [V/m]; phi (nullable) [V]
+ *   hip_stream  stream the kernels are enqueued on (NULL: the legacy default)
+ * Writes E (and phi) of every particle exactly as pp_field does for a context
+ * of this one bunch on the ordered-pair tiling (symmetric 0, i_per_lane 1,
+ * sum_tile 64, chunk_pairs_log2 22, grid_per_cu 4): the same bits.
+ * Asynchronous.  Calls on one device share its scratch, which keeps the last
+ * call's contents (each call rewrites all it reads): calls that overlap in
+ * time on one device (different streams, or different host threads) race and
+ * must be ordered by the caller.  Errors: PP_ERR_INVALID_ARG (null pointer,
+ * n out of range, weight <= 0, softening < 0, a layout beyond the scratch),
+ * PP_ERR_DEVICE (a HIP call failed); pp_last_error(NULL) holds the message. */
+#define PP_NOALLOC_MAX_N 65536
+#define PP_NOALLOC_SCRATCH_MIB 24
+pp_status pp_field_noalloc(int64_t n, const double *x, const double *y, const double *z, const double *q,
+                           double weight, double softening, pp_precision prec, double *ex, double *ey,
+                           double *ez, double *phi, void *hip_stream);
+
 /* Advance every bunch by n_steps >= 0 Velocity Verlet steps (Sec. 2.1,
  * Eqs. (G)/(H), with a = (q/m) E of Eqs. (D)/(F)), each step a plain sequence
  * of kernel launches.  The acceleration at the
@@ -278,7 +307,7 @@ int64_t pp_device_bytes(const pp_ctx *ctx);
 pp_status pp_destroy(pp_ctx *ctx);
 
 /* Last error message of ctx, or of the calling thread's last failed
- * pp_create when ctx is NULL.  Never NULL; "" when there was none.  The
+ * pp_create or pp_field_noalloc when ctx is NULL.  Never NULL; "" when there was none.  The
  * string lives until the next call on the same context (or thread). */
 const char *pp_last_error(const pp_ctx *ctx);
 

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libpp_hip.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pp_kernels.hip", "pp_sym.hip", "pp_sym64.hip", "pp_sort.hip", "pp_runtime.hip"]
+SOURCES = ["pp_kernels.hip", "pp_sym.hip", "pp_sym64.hip", "pp_sort.hip", "pp_runtime.hip", "pp_noalloc.hip"]
 ARCH = "gfx950"
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra",

@@ -30,7 +30,7 @@ PP_GRAPH = 1
 PP_AUTOTUNE = 2
 PP_CHECK = 4
 
-EXPORTS = ("pp_create", "pp_field", "pp_push", "pp_step_batched", "pp_diagnostics", "pp_invalidate",
+EXPORTS = ("pp_create", "pp_field", "pp_field_noalloc", "pp_push", "pp_step_batched", "pp_diagnostics", "pp_invalidate",
            "pp_get_tuning", "pp_set_tuning", "pp_time_field", "pp_set_profiling", "pp_get_profile",
            "pp_sync", "pp_device_bytes", "pp_destroy", "pp_last_error", "pp_abi_version")
 
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pp_create": ([ctypes.POINTER(_VP), ctypes.POINTER(Bunch), ctypes.c_int32, ctypes.c_int64,
                        ctypes.POINTER(State), ctypes.c_int, _VP], st),
         "pp_field": ([_VP, _VP, _VP, _VP, _VP], st),
+        "pp_field_noalloc": ([ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                              _VP, _VP, _VP, _VP, _VP], st),
         "pp_push": ([_VP, ctypes.c_int64], st),
         "pp_step_batched": ([_VP, ctypes.c_int64, ctypes.c_uint32], st),
         "pp_diagnostics": ([_VP, ctypes.POINTER(Diag)], st),
@@ -158,6 +160,16 @@ def pp_create(bunches: Sequence[Sequence[float]], n_total: int, state: Sequence[
 
 def pp_field(ctx, ex: int, ey: int, ez: int, phi: int | None = None) -> None:
     _check(load().pp_field(ctx, ex, ey, ez, phi or None), ctx)
+
+
+NOALLOC_MAX_N = 65536  # PP_NOALLOC_MAX_N of include/pp.h
+
+
+def pp_field_noalloc(n: int, x: int, y: int, z: int, q: int, weight: float, softening: float, precision: int,
+                     ex: int, ey: int, ez: int, phi: int | None = None, stream: int | None = None) -> None:
+    """Context-free, allocation-free field of one bunch (device pointers)."""
+    _check(load().pp_field_noalloc(int(n), x, y, z, q, float(weight), float(softening), int(precision),
+                                   ex, ey, ez, phi or None, _VP(stream) if stream else None), None)
 
 
 def pp_push(ctx, n_steps: int) -> None:

@@ -83,3 +83,20 @@ def test_package_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import\s+oracle|from\s+oracle|libpporacle|pp_oracle|oracle_\w+\()", txt), f
 
+
+def test_noalloc_rejects_bad_arguments_before_the_device(lib):
+    """pp_field_noalloc checks its arguments before any device call (here
+    there is no device) and reports through pp_last_error(NULL)."""
+    p = 0x1000
+    cases = [
+        ((0, p, p, p, p, 1.0, 0.0, pp.PP_MIXED, p, p, p, None, None), "1..65536"),
+        ((pp.NOALLOC_MAX_N + 1, p, p, p, p, 1.0, 0.0, pp.PP_MIXED, p, p, p, None, None), "allocation-free"),
+        ((10, None, p, p, p, 1.0, 0.0, pp.PP_FP64, p, p, p, None, None), "NULL"),
+        ((10, p, p, p, p, 1.0, 0.0, pp.PP_FP64, p, p, None, None, None), "NULL"),
+        ((10, p, p, p, p, 0.0, 0.0, pp.PP_FP64, p, p, p, None, None), "weight > 0"),
+        ((10, p, p, p, p, 1.0, float("nan"), pp.PP_FP64, p, p, p, None, None), "softening"),
+        ((10, p, p, p, p, 1.0, 0.0, 9, p, p, p, None, None), "precision"),
+    ]
+    for args, msg in cases:
+        assert lib.pp_field_noalloc(*args) == pp.PP_ERR_INVALID_ARG
+        assert msg in pp.pp_last_error(None)
