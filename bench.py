@@ -42,7 +42,7 @@ PEAK_FP64_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "pair_sym_cold_sphere_1m_counters.json")
 
 
-TUNING_KEYS = ("symmetric", "i_per_lane", "far_split", "sym_split")
+TUNING_KEYS = ("symmetric", "i_per_lane", "far_split", "sym_split", "fused")
 
 
 def stored_counters(workload, kernel, tuning):
@@ -79,12 +79,15 @@ def parse():
                    help="oracle threads for --mode oracle (0: every host core)")
     p.add_argument("--sizes", default="12288,16384,24576,32768,49152,65536,98304,131072",
                    help="particle counts for --mode tilings")
-    p.add_argument("--mode", default="throughput", choices=["throughput", "drift", "paper", "oracle", "tilings"],
+    p.add_argument("--mode", default="throughput",
+                   choices=["throughput", "drift", "paper", "oracle", "tilings", "steps", "ubench"],
                    help="drift: run --steps steps in mixed and FP64 precision and report the total-energy drift "
                         "and the mixed-vs-FP64 energy gap every --every steps (no timing line); paper: the "
                         "paper's own cube-lattice runs to 10 ns with the emittance series (--paper-cases); "
                         "oracle: time only the CPU oracle on --cpu-threads threads (no GPU); tilings: pair-stage time of "
-                        "the default tiling against the ordered kernel and the unsplit symmetric ones at --sizes")
+                        "the default tiling against the ordered kernel and the unsplit symmetric ones at --sizes; "
+                        "steps: per-step time (graph replay) of the default, the ordered and the fused tilings at "
+                        "--sizes; ubench: vector-ALU issue rates per clock per CU (micro-benchmarks)")
     p.add_argument("--paper-cases", default="main,dt,np,pic,long",
                    help="subset of main,dt,np,pic,long for --mode paper")
     p.add_argument("--every", type=int, default=20)
@@ -161,10 +164,10 @@ def tilings(a):
                 reps = max(3, min(50, int(4e10 / n ** 2)))
                 pp.pp_time_field(sim.ctx, 3 * reps)
                 cands = [("default", d),
-                         ("ordered", {**d, "symmetric": 0, "far_split": 0, "sym_split": 1,
+                         ("ordered", {**d, "symmetric": 0, "fused": 0, "far_split": 0, "sym_split": 1,
                                       "i_per_lane": 2 if (prec == "mixed" and n >= 16384) else 1})]
                 for k in (2, 4):
-                    cands.append((f"symmetric K={k} split 1", {**d, "symmetric": 1, "i_per_lane": k, "sym_split": 1,
+                    cands.append((f"symmetric K={k} split 1", {**d, "symmetric": 1, "fused": 0, "i_per_lane": k, "sym_split": 1,
                                                                 "far_split": 3 if prec == "mixed" else 0}))
                 best = {}
                 for _ in range(2):
@@ -176,6 +179,88 @@ def tilings(a):
             print(json.dumps({"mode": "tilings", "workload": a.workload, "precision": prec, "n": n,
                               "default_tuning": {k: d[k] for k in ("symmetric", "i_per_lane", "sym_split", "far_split")},
                               "pair_stage_ms": best}), flush=True)
+
+
+UBENCH_OPS = {  # name: (op code, lane operations per chain-iteration, iterations)
+    "fma_f32": (0, 1, 400000), "add_f32": (1, 1, 400000), "mul_f32": (2, 1, 400000),
+    "rsq_f32": (3, 1, 100000), "fma8_rsq_f32": (4, 9, 40000), "fma_f64": (5, 1, 200000)}
+
+
+def ubench(a):
+    """Vector-ALU issue rates of gfx950 (libpp_ubench.so): lane operations per
+    shader clock per compute unit for FP32 FMA, add, mul, v_rsq_f32, 8 FMA
+    interleaved with one rsq, and FP64 FMA.  8 workgroups of 256 threads per
+    CU, 8 independent chains per thread; the clock is measured inside the
+    kernel (shader-clock counter against the wall clock)."""
+    import ctypes
+    import torch
+    from paper_2502_10640_amd.build import UBENCH_PATH
+    L = ctypes.CDLL(UBENCH_PATH)
+    L.pp_ubench_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    L.pp_ubench_valu.restype = ctypes.c_int
+    L.pp_ubench_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    L.pp_ubench_wall_clock_khz.restype = ctypes.c_int
+    khz = ctypes.c_int(0)
+    assert L.pp_ubench_wall_clock_khz(ctypes.byref(khz)) == 0
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 8 * cus
+    inp = torch.rand(1024, device="cuda")
+    out = torch.empty(blocks * 256, device="cuda")
+    clk = torch.zeros(2 * blocks, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    res = {"mode": "ubench", "cus": cus, "wall_clock_khz": khz.value, "blocks": blocks, "threads_per_block": 256,
+           "chains_per_thread": 8, "ops": {}}
+    for name, (op, per, iters) in UBENCH_OPS.items():
+        ms = ctypes.c_double(0.0)
+        for it in (max(1, iters // 50), iters):  # warm-up, then the measured run
+            rc = L.pp_ubench_valu(op, blocks, it, inp.data_ptr(), out.data_ptr(), clk.data_ptr(), ctypes.byref(ms))
+            assert rc == 0, (name, rc)
+        c = clk.cpu().numpy()
+        cycles, ticks = float(c[0::2].mean()), float(c[1::2].mean())
+        clock_hz = cycles / ticks * khz.value * 1e3
+        lane_ops = blocks * 256 * 8 * iters * per
+        res["ops"][name] = {"ms": ms.value, "lane_ops": lane_ops, "clock_ghz": clock_hz / 1e9,
+                            "lane_ops_per_clock_per_cu": lane_ops / (cus * ms.value * 1e-3 * clock_hz),
+                            "lane_ops_per_block_span_per_cu": lane_ops / (cus * cycles)}
+        print(f"[ubench] {name}: {res['ops'][name]['lane_ops_per_clock_per_cu']:.1f} lane-ops/clock/CU "
+              f"at {clock_hz / 1e9:.2f} GHz", file=sys.stderr, flush=True)
+    print(json.dumps(res))
+
+
+def step_times(a):
+    """Per-step time (hipGraph replay) of the default tiling and of the
+    schedules that compete for small bunches -- the two-kernel ordered step,
+    and the fused step at 4..32 receivers per workgroup of 512 threads --
+    for --workload at each of --sizes.  Best of two timed runs; prints one
+    JSON line per precision and size."""
+    import torch
+    from paper_2502_10640_amd import workloads as wl
+    from paper_2502_10640_amd.sim import Simulation
+    cands = [("default", {}), ("ordered", {"symmetric": 0, "fused": 0, "far_split": 0, "sym_split": 1, "i_per_lane": 1})]
+    for r in (4, 8, 16, 32):
+        cands.append((f"fused R={r}", {"symmetric": 0, "fused": r, "far_split": 0, "sym_split": 1, "i_per_lane": 2}))
+    for prec in a.precisions.split(","):
+        for n in (int(x) for x in a.sizes.split(",")):
+            bunches = wl.workload(a.workload, n_override=n)
+            total = sum(b.n for b in bunches)
+            steps = max(50, min(2000, int(2e10 / total ** 2)))
+            res, default = {}, None
+            for name, tun in cands:
+                with Simulation(bunches, prec, tuning={**tun, "graph_steps": 50}) as sim:
+                    if default is None:
+                        default = {k: v for k, v in sim.tuning().items() if k != "graph_steps"}
+                    sim.step_batched(50, graph=True)
+                    torch.cuda.synchronize()
+                    best = float("inf")
+                    for _ in range(2):
+                        t0 = time.perf_counter()
+                        sim.step_batched(steps, graph=True)
+                        torch.cuda.synchronize()
+                        best = min(best, (time.perf_counter() - t0) / steps * 1e6)
+                res[name] = round(best, 2)
+            print(json.dumps({"mode": "steps", "workload": a.workload, "precision": prec, "n": total,
+                              "steps": steps, "default_tuning": default, "us_per_step": res}), flush=True)
 
 
 def total_energy(sim):
@@ -391,6 +476,12 @@ def main():
     if a.mode == "tilings":
         tilings(a)
         return
+    if a.mode == "ubench":
+        ubench(a)
+        return
+    if a.mode == "steps":
+        step_times(a)
+        return
     if a.calibrate_copy_mib:
         calibrate_copy(a.calibrate_copy_mib)
         return
@@ -432,6 +523,8 @@ def main():
     sym = used_tuning.get("symmetric", 0) == 1
     if sym:
         kernel = "pair_sym_kernel" if a.precision == "mixed" else "pair_sym64_kernel"
+    elif used_tuning.get("fused", 0):
+        kernel = "fused_kernel"  # the whole evaluation and its update in one kernel
     else:
         kernel = f"pair_{a.precision}_kernel"
     peak = PEAK_FP32_TFLOPS if a.precision == "mixed" else PEAK_FP64_TFLOPS

@@ -163,6 +163,17 @@ typedef struct {
                             fills the last wave of items.  Changes the order of
                             additions, hence the bits.  The ordered schedule
                             ignores it.                                         */
+  int32_t fused;         /* 0, or the fused small-bunch schedule with that many
+                            receivers per workgroup (4, 8, 16 or 32; needs
+                            symmetric 0 and far_split 0; i_per_lane 1, 2 or 4
+                            then gives workgroups of 256 x i_per_lane threads
+                            that split each receiver's sources; sum_tile,
+                            chunk_pairs_log2 and grid_per_cu do not apply):
+                            one workgroup computes the whole field of its
+                            receivers, every source of the bunch streamed
+                            through LDS, and applies the update itself, so a
+                            step is one kernel.  Changes the order of
+                            additions, hence the bits.                          */
 } pp_tuning;
 
 /* Create a context over n_bunches bunches of a state of n_total particles:
@@ -218,8 +229,9 @@ pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi)
  *   ex, ey, ez  device outputs of length n [V/m]; phi (nullable) [V]
  *   hip_stream  stream the kernels are enqueued on (NULL: the legacy default)
  * Writes E (and phi) of every particle exactly as pp_field does for a context
- * of this one bunch on the ordered-pair tiling (symmetric 0, i_per_lane 1,
- * sum_tile 64, chunk_pairs_log2 22, grid_per_cu 4): the same bits.
+ * of this one bunch on the ordered-pair tiling (symmetric 0, fused 0,
+ * i_per_lane 1, sum_tile 64, chunk_pairs_log2 22, grid_per_cu 4): the same
+ * bits.
  * Asynchronous.  Calls on one device share its scratch, which keeps the last
  * call's contents (each call rewrites all it reads): calls that overlap in
  * time on one device (different streams, or different host threads) race and

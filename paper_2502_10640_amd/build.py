@@ -1,8 +1,10 @@
 """Build the gfx950 shared library ``libpp_hip.so`` from ``csrc/`` with hipcc.
 
 Every HIP source is compiled with packed FP32 instructions disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``); gfx950 issues plain
-FP32 VALU operations at the full vector rate, so nothing is lost.
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``).  On gfx950 plain FP32
+FMA still issues 108 lane operations per clock per CU, 85% of the 128 that the
+packed FP32 peak assumes (``bench.py --mode ubench``,
+``profiles/valu_issue_rates.md``).
 """
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libpp_hip.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pp_kernels.hip", "pp_sym.hip", "pp_sym64.hip", "pp_sort.hip", "pp_runtime.hip", "pp_noalloc.hip"]
+SOURCES = ["pp_kernels.hip", "pp_sym.hip", "pp_sym64.hip", "pp_sort.hip", "pp_runtime.hip", "pp_noalloc.hip", "pp_fused.hip"]
 ARCH = "gfx950"
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra",
@@ -59,6 +61,25 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+UBENCH_SRC = "pp_ubench.hip"
+UBENCH_PATH = os.path.join(HERE, "libpp_ubench.so")
+
+
+def build_ubench(verbose: bool = False) -> str:
+    """The vector-ALU micro-benchmarks (``bench.py --mode ubench``): a library
+    of their own, outside the C ABI of include/pp.h."""
+    obj = _compile(UBENCH_SRC)
+    tmp = UBENCH_PATH + ".tmp"
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, UBENCH_PATH)
+    if verbose:
+        print("built", UBENCH_PATH)
+    return UBENCH_PATH
+
+
 def device_asm(src: str = "pp_kernels.hip") -> str:
     """gfx950 assembly of one source (for inspecting instruction selection)."""
     out = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".s")
@@ -70,3 +91,4 @@ def device_asm(src: str = "pp_kernels.hip") -> str:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_ubench(verbose=True)

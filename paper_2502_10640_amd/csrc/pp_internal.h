@@ -379,9 +379,8 @@ hipError_t launch_diag(const DiagArgs& a, int32_t n_bunches, hipStream_t s);
 hipError_t launch_fill_bid(int32_t* bid, int64_t n_total, const BunchDev* bunches, int32_t n_bunches,
                            hipStream_t s);
 int pair_regs_hint(bool mixed, int i_per_lane);
-// Fused small-bunch schedule: receivers per item, and the launch of one
-// evaluation (one workgroup per item).
-int fused_receivers_per_item(int i_per_lane, int lanes);
-hipError_t launch_fused(const FusedArgs& a, bool mixed, int i_per_lane, int lanes, FinalMode mode, bool uniform_q,
+// Fused small-bunch schedule: the launch of one evaluation, one workgroup of
+// `threads` (256, 512 or 1024) per item of `receivers` (4, 8, 16 or 32).
+hipError_t launch_fused(const FusedArgs& a, bool mixed, int receivers, int threads, FinalMode mode, bool uniform_q,
                         bool with_phi, int n_items, hipStream_t s);
 }  // namespace ppk

@@ -111,6 +111,15 @@ struct pp_ctx {
   float* gbox = nullptr;           // GBOX x 64-particle groups
   int64_t n_in = 0;                // particles inside bunches
   int32_t n_groups = 0, n_blocks = 0;
+  // fused small-bunch schedule: work list, the second source buffer (mixed:
+  // 6 mirror planes; FP64: 2 x 3 planes of positions) and which buffer holds
+  // the positions the next evaluation reads
+  ppk::FusedItem* fitems = nullptr;
+  size_t fitems_cap = 0;
+  int32_t n_fitems = 0;
+  float* mir2 = nullptr;
+  double* src64 = nullptr;
+  int cur = 0;
   void* hpin = nullptr;        // pinned host staging for every host<->device copy
   size_t hpin_bytes = 0;
 
@@ -139,6 +148,7 @@ struct pp_ctx {
   bool mixed() const { return prec == PP_MIXED; }
   bool sym() const { return tun.symmetric != 0; }
   bool far() const { return mixed() && sym() && tun.far_split > 0; }
+  bool fused() const { return tun.fused != 0; }
   size_t acc_elem() const { return mixed() ? sizeof(float) : sizeof(double); }
   int key_shift = 30, key_bits = 30;  // sort key layout of the far split (set_sort_bits)
   int64_t perm_k = -1;  // step index of the evaluation whose positions the current order sorts (-1: none)
@@ -398,6 +408,35 @@ pp_status build_sym(pp_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused small-bunch schedule: one item per R receivers of a bunch, the
+// items of the largest bunches first (their workgroups run longest); the
+// second source buffer of the kick-and-drift.
+// ---------------------------------------------------------------------------
+pp_status build_fused(pp_ctx* c) {
+  pp_status st;
+  const int64_t R = c->tun.fused;
+  std::vector<int> order(c->nb);
+  for (int b = 0; b < c->nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return c->hb[x].n > c->hb[y].n; });
+  std::vector<ppk::FusedItem> items;
+  for (int b : order) {
+    for (int64_t i0 = 0; i0 < c->hb[b].n; i0 += R) items.push_back({b, (int32_t)i0});
+  }
+  if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "fused schedule too long");
+  c->n_fitems = (int32_t)items.size();
+  if (items.size() > c->fitems_cap) {
+    c->fitems_cap = 0;
+    if ((st = release(c, c->fitems)) != PP_OK) return st;
+    PP_HIP(c, dalloc(c, &c->fitems, items.size()));
+    c->fitems_cap = items.size();
+  }
+  const size_t n = (size_t)c->n_total;
+  if (c->mixed() && !c->mir2) PP_HIP(c, dalloc(c, &c->mir2, 6 * n));
+  if (!c->mixed() && !c->src64) PP_HIP(c, dalloc(c, &c->src64, 6 * n));
+  return h2d(c, c->fitems, items.data(), items.size() * sizeof(ppk::FusedItem));
+}
+
+// ---------------------------------------------------------------------------
 // Work list: items (bunch, j-chunk, first receiver), heaviest first.  The
 // chunking rule is ppk::ordered_chunking.  Its fill cap (FILL_CHUNKS):
 // measured at 4096 particles (16^3 cube, hipGraph replay), 32 chunks were
@@ -477,6 +516,7 @@ pp_status build_items(pp_ctx* c) {
   pp_status s;
   if ((s = h2d(c, c->items, items.data(), items.size() * sizeof(WorkItem))) != PP_OK) return s;
   if ((s = h2d(c, c->dbunch, c->hbd.data(), c->hbd.size() * sizeof(BunchDev))) != PP_OK) return s;
+  if (c->fused()) return build_fused(c);
   return c->sym() ? build_sym(c) : PP_OK;
 }
 
@@ -520,6 +560,10 @@ ppk::PackArgs pack_args(pp_ctx* c) {
   if (c->mixed()) {
     a.xh = c->plane(0); a.yh = c->plane(1); a.zh = c->plane(2);
     a.xl = c->plane(3); a.yl = c->plane(4); a.zl = c->plane(5);
+  } else if (c->fused()) {
+    a.sx = c->src64;
+    a.sy = c->src64 + c->n_total;
+    a.sz = c->src64 + 2 * c->n_total;
   }
   a.counter = c->counter;
   return a;
@@ -568,6 +612,7 @@ hipEvent_t take_event(pp_ctx* c) {
 // The three launches of one evaluation, on stream s.
 pp_status enqueue_pack(pp_ctx* c, bool drift, hipStream_t s) {
   PP_LAUNCH(c, ppk::launch_pack(pack_args(c), drift, c->mixed(), s));
+  c->cur = 0;  // the pack writes the first source buffer
   return PP_OK;
 }
 
@@ -706,12 +751,55 @@ pp_status enqueue_final(pp_ctx* c, ppk::FinalMode mode, double* ex, double* ey, 
   return PP_OK;
 }
 
+// One field evaluation and its update (mode): the pair stage then the
+// combine kernel, or, on the fused schedule, one fused kernel reading the
+// source buffer that holds the current positions (the kick-and-drift writes
+// the other one).
+pp_status enqueue_eval(pp_ctx* c, ppk::FinalMode mode, double* ex, double* ey, double* ez, double* phi,
+                       hipStream_t s, bool timed, int64_t k) {
+  pp_status st;
+  if (!c->fused()) {
+    if ((st = enqueue_pair(c, phi != nullptr, s, timed, k)) != PP_OK) return st;
+    return enqueue_final(c, mode, ex, ey, ez, phi, s);
+  }
+  if (timed) ++c->prof_evals;
+  const size_t n = (size_t)c->n_total;
+  const int cur = c->cur, nxt = 1 - cur;
+  ppk::FusedArgs fa{};
+  fa.bunches = c->dbunch;
+  fa.items = c->fitems;
+  fa.upd = final_args(c);
+  fa.upd.ex = ex; fa.upd.ey = ey; fa.upd.ez = ez; fa.upd.phi = phi;
+  if (c->mixed()) {
+    // buffer 0: the mirror's planes 0-5; buffer 1: mir2; the charge plane is shared
+    auto buf = [&](int b, int p) { return b == 0 ? c->plane(p) : c->mir2 + (size_t)p * n; };
+    fa.xh = buf(cur, 0); fa.yh = buf(cur, 1); fa.zh = buf(cur, 2);
+    fa.xl = buf(cur, 3); fa.yl = buf(cur, 4); fa.zl = buf(cur, 5);
+    fa.qt = c->plane(6);
+    fa.upd.xh = buf(nxt, 0); fa.upd.yh = buf(nxt, 1); fa.upd.zh = buf(nxt, 2);
+    fa.upd.xl = buf(nxt, 3); fa.upd.yl = buf(nxt, 4); fa.upd.zl = buf(nxt, 5);
+  } else {
+    const double* sb = c->src64 + (size_t)cur * 3 * n;
+    fa.x = sb; fa.y = sb + n; fa.z = sb + 2 * n;
+    fa.qt64 = c->qt64;
+    double* nb = c->src64 + (size_t)nxt * 3 * n;
+    fa.upd.sx = nb; fa.upd.sy = nb + n; fa.upd.sz = nb + 2 * n;
+  }
+  if ((st = mark(c, timed, true, s)) != PP_OK) return st;
+  PP_LAUNCH(c, ppk::launch_fused(fa, c->mixed(), c->tun.fused, 256 * c->tun.i_per_lane, mode, c->uniform_q,
+                                 phi != nullptr, c->n_fitems, s));
+  if ((st = mark(c, timed, false, s)) != PP_OK) return st;
+  if (mode == ppk::FIN_KICK_DRIFT) c->cur = nxt;
+  return PP_OK;
+}
+
 pp_status ensure_accel(pp_ctx* c) {
   if (c->a_valid) return PP_OK;
   pp_status s;
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, false, c->stream, c->prof, c->step)) != PP_OK) return s;
-  if ((s = enqueue_final(c, ppk::FIN_ACCEL, nullptr, nullptr, nullptr, nullptr, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_eval(c, ppk::FIN_ACCEL, nullptr, nullptr, nullptr, nullptr, c->stream, c->prof, c->step)) !=
+      PP_OK)
+    return s;
   c->a_valid = true;
   return PP_OK;
 }
@@ -725,9 +813,8 @@ pp_status enqueue_steps(pp_ctx* c, int64_t n, hipStream_t s, bool timed) {
   if (n <= 0) return PP_OK;
   if ((r = enqueue_pack(c, true, s)) != PP_OK) return r;
   for (int64_t k = 0; k < n; ++k) {
-    if ((r = enqueue_pair(c, false, s, timed, c->step + k + 1)) != PP_OK) return r;
     const ppk::FinalMode m = k + 1 < n ? ppk::FIN_KICK_DRIFT : ppk::FIN_KICK;
-    if ((r = enqueue_final(c, m, nullptr, nullptr, nullptr, nullptr, s)) != PP_OK) return r;
+    if ((r = enqueue_eval(c, m, nullptr, nullptr, nullptr, nullptr, s, timed, c->step + k + 1)) != PP_OK) return r;
   }
   return PP_OK;
 }
@@ -795,6 +882,9 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   // parts per block pair: a divisor of the 8 (mixed) or 4 (FP64) groups of a
   // block at 1 receiver per lane
   if (!(t.sym_split == 1 || t.sym_split == 2 || t.sym_split == 4)) return false;
+  // fused: 4, 8, 16 or 32 receivers per workgroup, on the ordered layout
+  if (!(t.fused == 0 || t.fused == 4 || t.fused == 8 || t.fused == 16 || t.fused == 32)) return false;
+  if (t.fused && (t.symmetric || t.far_split || k > 4)) return false;
   return true;
 }
 
@@ -844,6 +934,9 @@ double list_makespan(double n_off, double c_off, double n_diag, double c_diag, d
 // over the resident slots times the slot count (idle slots in the last wave
 // included).
 constexpr double kSplitOverhead = 24.0;
+
+// Largest bunch the default tiling puts on the fused schedule.
+constexpr int64_t kFusedDefaultMaxN = 8192;
 
 pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   int64_t min_n = INT64_MAX;
@@ -901,6 +994,25 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
       }
     }
   }
+  // Small bunches: the fused schedule (one kernel per step).  Measured per
+  // step on MI355X with hipGraph replay against the two-kernel ordered step,
+  // at the fastest receivers per workgroup: 512 particles 9.8 -> 4.3 us,
+  // 2048 11.5 -> 6.7, 4096 17.3 -> 13.5, 8192 42.9 -> 38.2 (mixed; FP64
+  // 10.0 -> 4.2, 13.2 -> 7.5, 22.7 -> 16.4, 55.0 -> 49.0); at 16384 the
+  // ordered and symmetric schedules are faster.  The fastest tiling gives
+  // each CU about one workgroup of 512 threads: R = n / 256 receivers per
+  // workgroup, a power of two in 4..32.
+  int64_t max_n = 0;
+  for (const auto& b : hb) max_n = std::max<int64_t>(max_n, b.n);
+  if (max_n <= kFusedDefaultMaxN) {
+    int64_t R = 4;
+    while (R < 32 && 2 * R * 256 <= max_n) R *= 2;
+    t.symmetric = 0;
+    t.far_split = 0;
+    t.sym_split = 1;
+    t.fused = (int32_t)R;
+    t.i_per_lane = 2;
+  }
   return t;
 }
 
@@ -924,7 +1036,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v5";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v6";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -947,7 +1059,7 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
     std::string k, extra;
     pp_tuning v{};
     if (!(in >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
-          v.symmetric >> v.far_split >> v.sym_split) || (in >> extra))
+          v.symmetric >> v.far_split >> v.sym_split >> v.fused) || (in >> extra))
       continue;
     if (k == key) { *t = v; found = true; }
   }
@@ -972,10 +1084,13 @@ void tune_store(const std::string& key, const pp_tuning& t) {
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
-      << t.graph_steps << " " << t.symmetric << " " << t.far_split << " " << t.sym_split << "\n";
+      << t.graph_steps << " " << t.symmetric << " " << t.far_split << " " << t.sym_split << " " << t.fused << "\n";
 }
 
-pp_status time_eval(pp_ctx* c, int reps, double* ms) {
+// Time of one field evaluation: the pair stage (the sort, the pair-sum
+// dispatches, the folds; on the fused schedule the fused kernel, which also
+// combines), and with `full` also the combine kernel.
+pp_status time_eval(pp_ctx* c, int reps, double* ms, bool full = false) {
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return dev_fail(c, hipErrorOutOfMemory, "hipEventCreate");
   double tot = 0.0;
@@ -983,7 +1098,14 @@ pp_status time_eval(pp_ctx* c, int reps, double* ms) {
   for (int r = 0; r < reps && st == PP_OK; ++r) {
     if ((st = enqueue_pack(c, false, c->stream)) != PP_OK) break;
     PP_HIP(c, hipEventRecord(e0, c->stream));
-    if ((st = enqueue_pair(c, false, c->stream, false, c->step)) != PP_OK) break;
+    if (c->fused())
+      st = enqueue_eval(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, nullptr, c->stream, false, c->step);
+    else
+      st = enqueue_pair(c, false, c->stream, false, c->step);
+    if (st != PP_OK) break;
+    if (full && !c->fused() &&
+        (st = enqueue_final(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, nullptr, c->stream)) != PP_OK)
+      break;
     PP_HIP(c, hipEventRecord(e1, c->stream));
     PP_HIP(c, hipEventSynchronize(e1));
     float f = 0.f;
@@ -999,8 +1121,7 @@ pp_status time_eval(pp_ctx* c, int reps, double* ms) {
 pp_status field_into(pp_ctx* c, double* ex, double* ey, double* ez) {
   pp_status s;
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, false, c->stream, false, c->step)) != PP_OK) return s;
-  return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, nullptr, c->stream);
+  return enqueue_eval(c, ppk::FIN_FIELD, ex, ey, ez, nullptr, c->stream, false, c->step);
 }
 
 pp_status l2_rel(pp_ctx* c, const double* ref, const double* got, double* rel) {
@@ -1020,6 +1141,10 @@ pp_status l2_rel(pp_ctx* c, const double* ref, const double* got, double* rel) {
   return PP_OK;
 }
 
+// Largest bunch the autotuner tries the fused schedule on: each of its
+// workgroups streams the whole bunch, so its source traffic grows as n^2 / R.
+constexpr int64_t kFusedMaxN = 65536;
+
 pp_status autotune(pp_ctx* c) {
   const std::string key = tune_key(c);
   pp_tuning cached{};
@@ -1036,15 +1161,17 @@ pp_status autotune(pp_ctx* c) {
   if ((s = apply_tuning(c, best)) != PP_OK) return s;
   if ((s = field_into(c, ref, ref + c->n_total, ref + 2 * c->n_total)) != PP_OK) return s;
   double best_ms = 0.0;
-  if ((s = time_eval(c, 1, &best_ms)) != PP_OK) return s;   // warm-up
-  if ((s = time_eval(c, 2, &best_ms)) != PP_OK) return s;
+  // whole evaluations (the combine included), so that the fused schedule, which
+  // combines inside its one kernel, is compared fairly
+  if ((s = time_eval(c, 1, &best_ms, true)) != PP_OK) return s;   // warm-up
+  if ((s = time_eval(c, 2, &best_ms, true)) != PP_OK) return s;
   const double tol = c->mixed() ? 1e-6 : 1e-13;
   auto trial = [&](pp_tuning t) -> pp_status {
     if (!valid_tuning(t, c->mixed())) return PP_OK;
     pp_status r;
     if ((r = apply_tuning(c, t)) != PP_OK) return r;
     double ms = 0.0;
-    if ((r = time_eval(c, 2, &ms)) != PP_OK) return r;
+    if ((r = time_eval(c, 2, &ms, true)) != PP_OK) return r;
     if (ms < best_ms * 0.98) {
       if ((r = field_into(c, got, got + c->n_total, got + 2 * c->n_total)) != PP_OK) return r;
       double rel = 0.0;
@@ -1067,6 +1194,7 @@ pp_status autotune(pp_ctx* c) {
         t.symmetric = sym;
         t.i_per_lane = k;
         t.far_split = sym ? t.far_split : 0;
+        t.fused = 0;
         if ((s = trial(t)) != PP_OK) return s;
       }
     }
@@ -1079,6 +1207,21 @@ pp_status autotune(pp_ctx* c) {
       for (int sp : {1, 2, 4}) {
         pp_tuning t = best;
         t.sym_split = sp;
+        if ((s = trial(t)) != PP_OK) return s;
+      }
+    }
+  }
+  int64_t max_n = 0;
+  for (const auto& b : c->hb) max_n = std::max(max_n, b.n);
+  if (max_n <= kFusedMaxN) {
+    for (int rec : {4, 8, 16, 32}) {
+      for (int k : {1, 2, 4}) {
+        pp_tuning t = best;
+        t.symmetric = 0;
+        t.far_split = 0;
+        t.sym_split = 1;
+        t.fused = rec;
+        t.i_per_lane = k;
         if ((s = trial(t)) != PP_OK) return s;
       }
     }
@@ -1271,8 +1414,7 @@ pp_status pp_field(pp_ctx* c, double* ex, double* ey, double* ez, double* phi) {
   if ((s = usable(c)) != PP_OK) return s;
   if (!ex || !ey || !ez) return set_err(c, PP_ERR_INVALID_ARG, "field outputs must not be NULL");
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, phi != nullptr, c->stream, false, c->step)) != PP_OK) return s;
-  return enqueue_final(c, ppk::FIN_FIELD, ex, ey, ez, phi, c->stream);
+  return enqueue_eval(c, ppk::FIN_FIELD, ex, ey, ez, phi, c->stream, false, c->step);
 }
 
 pp_status pp_push(pp_ctx* c, int64_t n_steps) {
@@ -1335,8 +1477,8 @@ pp_status pp_diagnostics(pp_ctx* c, pp_diag* out) {
     c->diag_doubles = need;
   }
   if ((s = enqueue_pack(c, false, c->stream)) != PP_OK) return s;
-  if ((s = enqueue_pair(c, true, c->stream, false, c->step)) != PP_OK) return s;
-  if ((s = enqueue_final(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, c->phi, c->stream)) != PP_OK) return s;
+  if ((s = enqueue_eval(c, ppk::FIN_FIELD, nullptr, nullptr, nullptr, c->phi, c->stream, false, c->step)) != PP_OK)
+    return s;
   ppk::DiagArgs d{};
   d.bunches = c->dbunch;
   d.x = c->st.x; d.y = c->st.y; d.z = c->st.z;

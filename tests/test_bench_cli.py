@@ -11,7 +11,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("mode", ["throughput", "drift", "paper", "oracle", "tilings"])
+@pytest.mark.parametrize("mode", ["throughput", "drift", "paper", "oracle", "tilings", "steps", "ubench"])
 def test_bench_refuses_more_than_one_gpu(mode):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--mode", mode],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)

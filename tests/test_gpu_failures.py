@@ -33,7 +33,7 @@ def _calls(sim, prec):
     """A typical run: field, pushes, graph replays, diagnostics (lazy
     allocations), a change to the symmetric schedule (new work list, slots,
     sort buffers), an invalidation, a checked step, a sync."""
-    sym = {"symmetric": 1, "i_per_lane": 1, "far_split": 3 if prec == "mixed" else 0, "graph_steps": 2}
+    sym = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3 if prec == "mixed" else 0, "graph_steps": 2}
     return [("field", lambda: sim.field(want_phi=True)),
             ("push", lambda: sim.push(2)),
             ("step_graph", lambda: sim.step_batched(4, graph=True)),
@@ -123,7 +123,7 @@ def test_device_bytes_accounting(gpu):
         assert pp.pp_device_bytes(None) == before + n1 + n2
         s1.diagnostics()  # lazy diagnostics buffers
         assert pp.pp_device_bytes(s1.ctx) > n1
-        s1.set_tuning(symmetric=1, i_per_lane=1, far_split=3)  # slots and sort buffers
+        s1.set_tuning(symmetric=1, fused=0, i_per_lane=1, far_split=3)  # slots and sort buffers
         assert pp.pp_device_bytes(s1.ctx) > n1
         # the context's own scratch: at least the acceleration (24 B) and mirror (28 B) per particle
         assert n1 >= 52 * b.n
@@ -145,7 +145,7 @@ def test_invalidate_recentres_the_mixed_frame(gpu):
     moved.x = b.x + shift
     say(f"invalidate re-centres the frame after a shift of {shift:.3e} m")
     ref = oracle_field(orc, moved)
-    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3}
     with Sim([b], "mixed", tuning=tun) as sim:
         at_origin = {k: v.cpu().numpy() for k, v in sim.field(want_phi=True).items()}
         ms_origin, _ = pp.pp_time_field(sim.ctx, 3)

@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
 PRECS = ["fp64", "mixed"]
+# the two-kernel ordered-pair schedule (small bunches default to the fused one)
+ORDERED_TUNING = {"symmetric": 0, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 1}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -113,7 +115,7 @@ def test_three_hundred_small_bunches(orc, sched):
     sizes = [int(v) for v in rng.integers(1, 101, 300)]
     bunches = [wl.cold_sphere(n, 20e-6, 1e4 * n, 1e-3, 0.01, 0, seed=5000 + k, name=f"s{k}")
                for k, n in enumerate(sizes)]
-    tun = None if sched == "ordered" else {"symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    tun = ORDERED_TUNING if sched == "ordered" else {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3}
     say(f"300 small bunches ({sched}), {sum(sizes)} particles")
     with Sim(bunches, "mixed", tuning=tun) as sim:
         full = gpu_field(sim)
@@ -132,9 +134,10 @@ def test_three_hundred_small_bunches(orc, sched):
     print(f"    worst relative L2 over the bunches {worst:.3e}", flush=True)
 
 
-RAGGED_TUNINGS = {"ordered": None, "symmetric": {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 1},
-                  "symmetric_k4": {"symmetric": 1, "i_per_lane": 4, "far_split": 0, "sym_split": 1},
-                  "symmetric_k2_split4": {"symmetric": 1, "i_per_lane": 2, "far_split": 0, "sym_split": 4}}
+RAGGED_TUNINGS = {"ordered": {"symmetric": 0, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 1},
+                  "symmetric": {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 1},
+                  "symmetric_k4": {"symmetric": 1, "fused": 0, "i_per_lane": 4, "far_split": 0, "sym_split": 1},
+                  "symmetric_k2_split4": {"symmetric": 1, "fused": 0, "i_per_lane": 2, "far_split": 0, "sym_split": 4}}
 
 
 @pytest.mark.parametrize("sched", list(RAGGED_TUNINGS))
@@ -171,7 +174,8 @@ def test_every_tiling_within_tolerance(orc, prec):
             for ts in (32, 256):
                 for cl in (16, 22):
                     for gpc in (1, 4):
-                        sim.set_tuning(i_per_lane=k, sum_tile=ts, chunk_pairs_log2=cl, grid_per_cu=gpc)
+                        sim.set_tuning(symmetric=0, fused=0, far_split=0, sym_split=1, i_per_lane=k, sum_tile=ts,
+                                       chunk_pairs_log2=cl, grid_per_cu=gpc)
                         check_field(gpu_field(sim), ref, TOL[prec], f"K={k} ts={ts} cl={cl} gpc={gpc}")
 
 
@@ -179,14 +183,15 @@ def _state(b):
     return OracleState(b.x, b.y, b.z, b.vx, b.vy, b.vz, b.q, b.m, b.weight, b.softening, b.dt)
 
 
+@pytest.mark.parametrize("sched", ["default", "ordered"])
 @pytest.mark.parametrize("prec", PRECS)
-def test_push_parity(orc, prec):
+def test_push_parity(orc, prec, sched):
     b = wl.workload("gaussian_65536", n_override=1024)[0]
     steps = 25
-    say(f"push {prec} n={b.n} steps={steps}")
+    say(f"push {prec} {sched} n={b.n} steps={steps}")
     s = _state(b)
     orc.vv(s, steps)
-    with Sim([b], prec) as sim:
+    with Sim([b], prec, tuning=None if sched == "default" else ORDERED_TUNING) as sim:
         sim.push(steps)
         g = {k: sim.host(k) for k in ("x", "y", "z", "vx", "vy", "vz")}
     r_rms = math.sqrt(np.mean(s.x ** 2 + s.y ** 2 + s.z ** 2))
@@ -202,9 +207,9 @@ DIAG_SCALARS = ("kinetic", "potential", "total")
 DIAG_VECTORS = ("com", "com_velocity", "emittance", "emittance_centered", "x_rms", "x_max", "v_rms", "v_max")
 
 
-DIAG_TUNING = {"fp64": None, "mixed": None,
-               "mixed_symmetric_far": {"symmetric": 1, "i_per_lane": 1, "far_split": 3},
-               "fp64_symmetric": {"symmetric": 1, "i_per_lane": 1}}
+DIAG_TUNING = {"fp64": None, "mixed": None, "fp64_ordered": ORDERED_TUNING, "mixed_ordered": ORDERED_TUNING,
+               "mixed_symmetric_far": {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3},
+               "fp64_symmetric": {"symmetric": 1, "fused": 0, "i_per_lane": 1}}
 
 
 @pytest.mark.parametrize("variant", list(DIAG_TUNING))
@@ -276,21 +281,21 @@ def test_push_equals_step_batched_bitwise(prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_batch_equals_separate_contexts_bitwise(prec):
-    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 0, "far_split": 0, "sym_split": 1})
+    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 0, "fused": 0, "far_split": 0, "sym_split": 1})
 
 
 def test_symmetric_far_batch_equals_separate_contexts_bitwise():
     # the sort keys, the coordinate bound, the boxes and the fold are all per bunch
-    _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "far_split": 3, "sym_split": 1})
+    _batch_equals_separate("mixed", {"i_per_lane": 1, "symmetric": 1, "fused": 0, "far_split": 3, "sym_split": 1})
 
 
 def test_fp64_symmetric_batch_equals_separate_contexts_bitwise():
-    _batch_equals_separate("fp64", {"i_per_lane": 1, "symmetric": 1, "far_split": 0, "sym_split": 1})
+    _batch_equals_separate("fp64", {"i_per_lane": 1, "symmetric": 1, "fused": 0, "far_split": 0, "sym_split": 1})
 
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_split_symmetric_batch_equals_separate_contexts_bitwise(prec):
-    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 1, "far_split": 3 if prec == "mixed" else 0,
+    _batch_equals_separate(prec, {"i_per_lane": 1, "symmetric": 1, "fused": 0, "far_split": 3 if prec == "mixed" else 0,
                                   "sym_split": 2})
 
 
@@ -389,7 +394,7 @@ def test_invalid_tuning_rejected():
     say("invalid tuning")
     with Sim([b], "fp64") as sim:
         for bad in ({"i_per_lane": 3}, {"i_per_lane": 8}, {"sum_tile": 48}, {"grid_per_cu": 0},
-                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}, {"symmetric": 1, "i_per_lane": 8}):
+                    {"chunk_pairs_log2": 40}, {"graph_steps": 0}, {"symmetric": 1, "fused": 0, "i_per_lane": 8}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
             assert e.value.status == pp.PP_ERR_INVALID_ARG
@@ -420,7 +425,7 @@ def test_split_with_many_slot_bands_sampled_parity_1m(orc, prec):
     b = wl.workload("cold_sphere_1m")[0]
     rng = np.random.default_rng(98)
     recv = np.sort(rng.choice(b.n, 256, replace=False))
-    tun = {"symmetric": 1, "i_per_lane": 4, "sym_split": 2, "far_split": 3 if prec == "mixed" else 0}
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 4, "sym_split": 2, "far_split": 3 if prec == "mixed" else 0}
     say(f"split 2 with slot bands, cold_sphere_1m {prec}")
     with Sim([b], prec, tuning=tun) as sim:
         got = gpu_field(sim, sl=recv)
@@ -444,7 +449,7 @@ def test_symmetric_field_parity(orc, prec, K, split):
     # over parts of the source block, folded in a fixed order
     bunches = _sym_bunches()
     say(f"symmetric field {prec} K={K} split={split} sizes={[b.n for b in bunches]}")
-    with Sim(bunches, prec, tuning={"symmetric": 1, "i_per_lane": K, "far_split": 0, "sym_split": split}) as sim:
+    with Sim(bunches, prec, tuning={"symmetric": 1, "fused": 0, "i_per_lane": K, "far_split": 0, "sym_split": split}) as sim:
         assert sim.tuning()["symmetric"] == 1 and sim.tuning()["sym_split"] == split
         full = gpu_field(sim)
         for k, b in enumerate(bunches):
@@ -458,7 +463,7 @@ def test_symmetric_field_parity(orc, prec, K, split):
 def test_symmetric_push_graph_and_trajectory(orc, prec, K, split):
     b = wl.workload("gaussian_65536", n_override=2500)[0]
     say(f"symmetric push == step_batched(graph) and trajectory vs oracle, 8 steps, {prec}, K={K} split={split}")
-    tun = {"symmetric": 1, "i_per_lane": K, "graph_steps": 3, "sym_split": split}
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": K, "graph_steps": 3, "sym_split": split}
     res = []
     for mode in ("push", "graph"):
         with Sim([b], prec, tuning=tun) as sim:
@@ -503,7 +508,7 @@ def test_symmetric_equals_itself_run_to_run(prec):
     say(f"symmetric run-to-run bitwise {prec}")
     outs = []
     for _ in range(2):
-        with Sim([b], prec, tuning={"symmetric": 1, "i_per_lane": 2}) as sim:
+        with Sim([b], prec, tuning={"symmetric": 1, "fused": 0, "i_per_lane": 2}) as sim:
             outs.append(gpu_field(sim))
     for k in outs[0]:
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
@@ -529,7 +534,7 @@ def _far_bound(f):
 def test_far_split_field_parity(orc, K, far, split):
     bunches = _far_bunches()
     say(f"far split field K={K} far={far} split={split} sizes={[b.n for b in bunches]} gap=3")
-    base = {"symmetric": 1, "i_per_lane": K, "sym_split": split}
+    base = {"symmetric": 1, "fused": 0, "i_per_lane": K, "sym_split": split}
     with Sim(bunches, "mixed", tuning={**base, "far_split": far}, gap=3) as sim:
         assert sim.tuning()["far_split"] == far
         got_far = gpu_field(sim)
@@ -559,7 +564,7 @@ def test_far_split_field_parity(orc, K, far, split):
 def test_far_split_push_graph_run_to_run_and_trajectory(orc, split):
     b = wl.workload("gaussian_65536", n_override=9000)[0]
     say(f"far split push == step_batched(graph), run-to-run, trajectory vs oracle, 6 steps, split={split}")
-    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3, "graph_steps": 2, "sym_split": split}
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3, "graph_steps": 2, "sym_split": split}
     res = []
     for mode in ("push", "graph", "push"):
         with Sim([b], "mixed", tuning=tun) as sim:
@@ -583,18 +588,18 @@ def test_far_split_tuning_rules():
     b = wl.workload("cold_sphere_2048", n_override=64)[0]
     say("far split tuning validation")
     with Sim([b], "mixed") as sim:
-        for bad in ({"symmetric": 0, "far_split": 2}, {"symmetric": 1, "i_per_lane": 1, "far_split": 5},
-                    {"symmetric": 1, "i_per_lane": 1, "far_split": -1},
-                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 3},
-                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 0},
-                    {"symmetric": 1, "i_per_lane": 1, "far_split": 0, "sym_split": 8}):
+        for bad in ({"symmetric": 0, "fused": 0, "far_split": 2}, {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 5},
+                    {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": -1},
+                    {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 3},
+                    {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 0},
+                    {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 8}):
             with pytest.raises(pp.PPError) as e:
                 sim.set_tuning(**bad)
             assert e.value.status == pp.PP_ERR_INVALID_ARG
     with Sim([b], "fp64") as sim:
         with pytest.raises(pp.PPError):
-            sim.set_tuning(symmetric=1, i_per_lane=1, far_split=1)
-        sim.set_tuning(symmetric=1, i_per_lane=2, far_split=0)   # symmetric FP64 has no far split
+            sim.set_tuning(symmetric=1, fused=0, i_per_lane=1, far_split=1)
+        sim.set_tuning(symmetric=1, fused=0, i_per_lane=2, far_split=0)   # symmetric FP64 has no far split
 
 
 def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatch):
@@ -604,7 +609,7 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     b = wl.workload("gaussian_65536", n_override=20000)[0]
     cache = tmp_path / "it's a" / "new dir" / "tune.txt"  # created without a shell, quotes and all
     monkeypatch.setenv("PP_TUNE_CACHE", str(cache))
-    junk = "not a record\ngfx950:old:format 1 64 22 4 16 0\n"  # skipped, and must not shift later records
+    junk = "not a record\ngfx950:old:format 1 64 22 4 16 0 3 1\n"  # skipped, and must not shift later records
     say(f"autotune mixed n={b.n}, cache {cache}")
     with Sim([b], "mixed") as sim:
         cache.parent.mkdir(parents=True)
@@ -620,10 +625,10 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     lines = cache.read_text().splitlines()
     assert lines[:2] == junk.splitlines() and len(lines) == 3
     line = lines[2].split()
-    assert len(line) == 9 and line[0].startswith("gfx950:")
+    assert len(line) == 10 and line[0].startswith("gfx950:")
     assert [int(v) for v in line[1:]] == [tuned[k] for k in ("i_per_lane", "sum_tile", "chunk_pairs_log2",
                                                                "grid_per_cu", "graph_steps", "symmetric",
-                                                               "far_split", "sym_split")]
+                                                               "far_split", "sym_split", "fused")]
     with Sim([b], "mixed") as sim:
         sim.step_batched(1, graph=False, autotune=True)
         assert sim.tuning() == tuned
@@ -721,7 +726,7 @@ def test_graph_replays_match_eager_steps_one_by_one(variant):
     replay the state equals that of a twin context stepped without graphs."""
     tun = {"graph_steps": 4}
     if variant == "symmetric_far":
-        tun.update({"symmetric": 1, "i_per_lane": 1, "far_split": 3})
+        tun.update({"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3})
     b = wl.workload("gaussian_65536", n_override=5000)[0]
     say(f"graph replays one by one ({variant})")
     with Sim([b], "mixed", tuning=tun) as g, Sim([b], "mixed", tuning=tun) as e:
@@ -740,7 +745,7 @@ def test_far_split_order_reuse_matches_one_step_pushes():
     rule), diagnostics and field evaluations between calls, and an
     invalidation at a step that is not a multiple of 8 must give the bits of a
     twin context advanced by one-step pushes with the same invalidation."""
-    tun = {"graph_steps": 3, "symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    tun = {"graph_steps": 3, "symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3}
     b = wl.workload("gaussian_65536", n_override=6000)[0]
     say("far split order reuse vs one-step pushes (graphs of 3, diagnostics, invalidation at step 5)")
     with Sim([b], "mixed", tuning=tun) as g, Sim([b], "mixed", tuning=tun) as e:
@@ -788,7 +793,7 @@ def test_two_body_closed_form_over_eleven_decades(prec, sched):
         r = (dx * dx + dy * dy + dz * dz).sqrt()
         f = k * Decimal(repr(w)) * Decimal(repr(-wl.E_CHARGE)) / (r * r * r)
         expect.append([float(f * dx), float(f * dy), float(f * dz)])  # on particle 0; particle 1 opposite
-    tun = None if sched == "ordered" else {"symmetric": 1, "i_per_lane": 1}
+    tun = ORDERED_TUNING if sched == "ordered" else {"symmetric": 1, "fused": 0, "i_per_lane": 1}
     say(f"{prec} two-body closed form, 32 separations 1e-9..1e2 m ({sched})")
     with Sim(bunches, prec, tuning=tun) as sim:
         f = gpu_field(sim)
@@ -809,7 +814,7 @@ def test_time_field_and_profile_leave_the_run_unchanged():
     neither it nor the event profiling changes a run's bits: 3 steps, a timed
     field, 3 more steps with profiling on equal 6 plain steps (far split on,
     so the order-reuse rule is exercised too)."""
-    tun = {"symmetric": 1, "i_per_lane": 1, "far_split": 3}
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 3}
     b = wl.workload("gaussian_65536", n_override=5000)[0]
     say("pp_time_field and profiling leave the trajectory unchanged")
     with Sim([b], "mixed", tuning=tun) as t, Sim([b], "mixed", tuning=tun) as e:

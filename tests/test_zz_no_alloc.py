@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
 PREC = {"fp64": pp.PP_FP64, "mixed": pp.PP_MIXED}
-ORDERED = {"symmetric": 0, "i_per_lane": 1, "sum_tile": 64, "chunk_pairs_log2": 22, "grid_per_cu": 4,
+ORDERED = {"symmetric": 0, "fused": 0, "i_per_lane": 1, "sum_tile": 64, "chunk_pairs_log2": 22, "grid_per_cu": 4,
            "far_split": 0, "sym_split": 1}
 
 
