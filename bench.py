@@ -42,7 +42,7 @@ PEAK_FP64_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "pair_sym_cold_sphere_1m_counters.json")
 
 
-TUNING_KEYS = ("symmetric", "i_per_lane", "far_split", "sym_split", "fused")
+TUNING_KEYS = ("symmetric", "i_per_lane", "far_split", "sym_split", "fused", "sym_rounds")
 
 
 def stored_counters(workload, kernel, tuning):

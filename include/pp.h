@@ -174,6 +174,14 @@ typedef struct {
                             through LDS, and applies the update itself, so a
                             step is one kernel.  Changes the order of
                             additions, hence the bits.                          */
+  int32_t sym_rounds;    /* symmetric only: 1, 2, 4 or 8 consecutive rounds per
+                            item for bunches of at least 32 x sym_rounds
+                            blocks (others: 1).  An item then keeps its
+                            receiver block in registers across that many
+                            source blocks: one receiver-side partial instead
+                            of one per round, and the receiver block read once
+                            (less slot and mirror traffic, longer items).
+                            Changes the order of additions, hence the bits.    */
 } pp_tuning;
 
 /* Create a context over n_bunches bunches of a state of n_total particles:

@@ -186,7 +186,10 @@ constexpr int N_PLANES = 8;
 constexpr int SYM_WAVES = 8;
 constexpr int SYM_WG = SYM_WAVES * 64;
 constexpr int SYM_PLANES = 16;  // Si(xyz) Ci(xyz) Sj(xyz) Cj(xyz) Sip Cip Sjp Cjp
-constexpr int SLOT_PLANES = 8;  // per slot: S(xyz) C(xyz) Sp Cp
+// per slot: one value per component, the item's compensated partial (S, C)
+// rounded to S + C (x, y, z, potential): one rounding of relative size u per
+// item partial, below the bounds of the plain sums it comes from
+constexpr int SLOT_PLANES = 4;
 
 struct SymItem {
   int32_t b;
@@ -195,7 +198,32 @@ struct SymItem {
   // sub-round r * split + h: round r of block pairs (0 = diagonal) and the
   // part h < split of source block J's 64-source groups that the item sweeps
   int32_t r;
+  // rounds the item sweeps, r, r + 1, ..., r + nr - 1 (source blocks
+  // I + r .. I + r + nr - 1 mod the bunch's block count), all part h; its
+  // receiver side is one partial over all of them (1 for diagonal items)
+  int32_t nr;
 };
+
+// Receiver-side rounds per item of a bunch of nbk blocks for the tuning value
+// sym_rounds (1, 2, 4 or 8): the value where the bunch has at least
+// 32 sym_rounds blocks, else 1 (mid-size bunches keep every item short, so
+// that the last wave of items stays full).  Groups of rounds start at rounds
+// 1, 1 + M, 1 + 2 M, ...; depends only on the bunch's size and the tuning.
+__host__ __device__ inline int sym_rounds_for(int64_t nbk, int sym_rounds) {
+  return nbk >= 32 * (int64_t)sym_rounds ? sym_rounds : 1;
+}
+
+// Rounds of the group that starts at round r (r >= 1, (r - 1) % M == 0) for
+// receiver block X of a bunch of nbk blocks: M rounds, fewer at the last
+// group, and without the half round nbk / 2 of an even block count where
+// X >= nbk / 2 (that round holds only I < nbk / 2).  0: no item.
+__host__ __device__ inline int sym_group_rounds(int64_t nbk, int M, int64_t r, int64_t X) {
+  const int64_t half = nbk / 2;
+  int64_t nr = half - r + 1 < M ? half - r + 1 : M;
+  if (nr <= 0) return 0;
+  if (nbk % 2 == 0 && r + nr - 1 == half && X >= half) --nr;
+  return (int)nr;
+}
 
 struct SymArgs {
   const BunchDev* bunches;
@@ -230,6 +258,7 @@ struct SymFoldArgs {
   int32_t nbt;
   int32_t block_size;
   int32_t split;
+  int32_t rounds;          // the sym_rounds tuning value
 };
 
 // Spatial sort (pp_sort.hip): keys per tile of the radix sort.

@@ -312,7 +312,7 @@ pp_status d2h(pp_ctx* c, void* dst, const void* src, size_t bytes) {
 // Rounds are grouped into bands whose partial slots fit in kSlotBytes; a band
 // is one launch of all its items followed by one fold.
 // ---------------------------------------------------------------------------
-constexpr size_t kSlotBytes = size_t(8) << 30;
+constexpr size_t kSlotBytes = size_t(12) << 30;
 
 // Sort key layout of the far split: each bunch's Morton code is as fine as its
 // own size asks (morton_bits_for), the bunch index sits above the widest code.
@@ -330,15 +330,21 @@ pp_status build_sym(pp_ctx* c) {
   set_sort_bits(c);
   const int64_t BS = c->sym_block();
   const int64_t S = c->tun.sym_split;
-  // sub-round d * S + h holds part h of every block pair of round d (round 0:
-  // the diagonal blocks); round_first[v] is the first item of sub-round v
+  const int M = c->tun.sym_rounds;
+  // Sub-round d * S + h holds part h of every block pair of round d (round 0:
+  // the diagonal blocks).  An item of a bunch with M_b = sym_rounds_for(...)
+  // rounds per item sweeps rounds d .. d + nr - 1 (a group starting at round
+  // 1, 1 + M_b, ...) and is listed at the sub-round of its first round;
+  // round_first[v] is the first item listed at sub-round v.
   std::vector<ppk::SymItem> items;
   std::vector<int64_t> round_first;
   int64_t maxr = 0;
+  int Mmax = 1;
   for (int b = 0; b < c->nb; ++b) {
     const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
     if (nbk > INT32_MAX / 8) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule: too many blocks");
     maxr = std::max(maxr, nbk / 2);
+    Mmax = std::max(Mmax, ppk::sym_rounds_for(nbk, M));
   }
   for (int64_t d = 0; d <= maxr; ++d) {
     for (int64_t h = 0; h < S; ++h) {
@@ -347,9 +353,15 @@ pp_status build_sym(pp_ctx* c) {
       for (int b = 0; b < c->nb; ++b) {
         const int64_t nbk = (c->hb[b].n + BS - 1) / BS;
         if (d > nbk / 2) continue;
+        if (d == 0) {
+          for (int64_t I = 0; I < nbk; ++I) items.push_back({b, (int32_t)I, (int32_t)I, v, 1});
+          continue;
+        }
+        const int Mb = ppk::sym_rounds_for(nbk, M);
+        if ((d - 1) % Mb != 0) continue;  // not the first round of a group
         for (int64_t I = 0; I < nbk; ++I) {
-          if (d > 0 && 2 * d == nbk && I >= nbk / 2) continue;
-          items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), v});
+          const int nr = ppk::sym_group_rounds(nbk, Mb, d, I);
+          if (nr > 0) items.push_back({b, (int32_t)I, (int32_t)((I + d) % nbk), v, nr});
         }
       }
     }
@@ -358,13 +370,24 @@ pp_status build_sym(pp_ctx* c) {
   if (items.size() > (size_t)INT32_MAX) return set_err(c, PP_ERR_INVALID_ARG, "symmetric schedule too long");
   const int64_t rounds = (maxr + 1) * S;
   const size_t per_round = (size_t)c->n_blocks * 2 * ppk::SLOT_PLANES * (size_t)BS * c->acc_elem();
-  // the fewest bands that fit, of equal size (no short last band leaving the GPU half idle)
-  const int64_t band_max = std::max<int64_t>(1, std::min<int64_t>(rounds, (int64_t)(kSlotBytes / per_round)));
-  const int64_t n_bands = (rounds + band_max - 1) / band_max;
-  const int64_t band = (rounds + n_bands - 1) / n_bands;
+  // Bands hold whole units of rounds (round 0, then groups of Mmax rounds, so
+  // that no item's rounds fall in two bands): the fewest bands whose slots
+  // fit, with the units shared out evenly (no short last band leaving the
+  // GPU half idle).
+  std::vector<int64_t> ub{0};
+  for (int64_t d = 0; d <= maxr; d = (d == 0 ? 1 : d + Mmax)) ub.push_back(std::min(rounds, (d == 0 ? 1 : d + Mmax) * S));
+  const int64_t n_units = (int64_t)ub.size() - 1;
+  const int64_t cap = std::max<int64_t>(1, (int64_t)(kSlotBytes / per_round));
+  int64_t per_band = n_units, band = 0;
+  for (int64_t nbands = 1; nbands <= n_units; ++nbands) {
+    per_band = (n_units + nbands - 1) / nbands;
+    band = 0;
+    for (int64_t u = 0; u < n_units; u += per_band) band = std::max(band, ub[std::min(n_units, u + per_band)] - ub[u]);
+    if (band <= cap || per_band == 1) break;
+  }
   c->bands.clear();
-  for (int64_t r0 = 0; r0 < rounds; r0 += band) {
-    const int64_t r1 = std::min(rounds, r0 + band);
+  for (int64_t u = 0; u < n_units; u += per_band) {
+    const int64_t r0 = ub[u], r1 = ub[std::min(n_units, u + per_band)];
     c->bands.push_back({(int32_t)round_first[r0], (int32_t)(round_first[r1] - round_first[r0]), (int32_t)r0,
                         (int32_t)r1});
   }
@@ -373,7 +396,7 @@ pp_status build_sym(pp_ctx* c) {
   // the launch (longest-first list scheduling).  Items are independent and the
   // fold adds slots in sub-round order, so the order changes no result.
   {
-    const int64_t r1 = std::min(rounds, band);
+    const int64_t r1 = c->bands.front().r1;
     std::rotate(items.begin() + round_first[0], items.begin() + round_first[std::min(S, r1)],
                 items.begin() + round_first[r1]);
   }
@@ -662,6 +685,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     fa.nbt = c->n_blocks;
     fa.block_size = (int32_t)c->sym_block();
     fa.split = c->tun.sym_split;
+    fa.rounds = c->tun.sym_rounds;
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
@@ -725,6 +749,7 @@ pp_status enqueue_pair(pp_ctx* c, bool phi, hipStream_t s, bool timed, int64_t k
     fa.nbt = c->n_blocks;
     fa.block_size = (int32_t)c->sym_block();
     fa.split = c->tun.sym_split;
+    fa.rounds = c->tun.sym_rounds;
     for (const auto& B : c->bands) {
       sa.r0 = B.r0;
       if ((st = mark(c, timed, true, s)) != PP_OK) return st;
@@ -882,6 +907,8 @@ bool valid_tuning(const pp_tuning& t, bool mixed) {
   // parts per block pair: a divisor of the 8 (mixed) or 4 (FP64) groups of a
   // block at 1 receiver per lane
   if (!(t.sym_split == 1 || t.sym_split == 2 || t.sym_split == 4)) return false;
+  // receiver-side rounds per symmetric item
+  if (!(t.sym_rounds == 1 || t.sym_rounds == 2 || t.sym_rounds == 4 || t.sym_rounds == 8)) return false;
   // fused: 4, 8, 16 or 32 receivers per workgroup, on the ordered layout
   if (!(t.fused == 0 || t.fused == 4 || t.fused == 8 || t.fused == 16 || t.fused == 32)) return false;
   if (t.fused && (t.symmetric || t.far_split || k > 4)) return false;
@@ -953,6 +980,11 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   t.graph_steps = 16;
   t.symmetric = 0;
   t.sym_split = 1;
+  // 8 rounds per symmetric item where a bunch has 256 blocks or more
+  // (sym_rounds_for): at 1M particles the fold and the rest of the step
+  // outside the pair kernel 1.65 -> 1.19 ms (mixed), 4.9 -> 3.0 ms (FP64),
+  // the pair kernel unchanged (`bench.py --tuning sym_rounds=1` against 8)
+  t.sym_rounds = 8;
   struct Variant { int k; double bs, eff; int blocks_per_cu; };
   std::vector<Variant> vars;
   if (mixed) {
@@ -1036,7 +1068,7 @@ std::string tune_key(pp_ctx* c) {
   const int lb = (int)std::lround(std::log2((double)c->nb));
   std::ostringstream o;
   o << "gfx950:" << c->cus << ":" << (c->mixed() ? "mixed" : "fp64") << ":p" << lp << ":b" << lb
-    << ":q" << (c->uniform_q ? 1 : 0) << ":v6";
+    << ":q" << (c->uniform_q ? 1 : 0) << ":v7";
   std::string s = o.str();
   for (auto& ch : s)
     if (ch == ' ') ch = '_';
@@ -1059,7 +1091,7 @@ bool tune_lookup(const std::string& key, pp_tuning* t) {
     std::string k, extra;
     pp_tuning v{};
     if (!(in >> k >> v.i_per_lane >> v.sum_tile >> v.chunk_pairs_log2 >> v.grid_per_cu >> v.graph_steps >>
-          v.symmetric >> v.far_split >> v.sym_split >> v.fused) || (in >> extra))
+          v.symmetric >> v.far_split >> v.sym_split >> v.fused >> v.sym_rounds) || (in >> extra))
       continue;
     if (k == key) { *t = v; found = true; }
   }
@@ -1084,7 +1116,8 @@ void tune_store(const std::string& key, const pp_tuning& t) {
   std::ofstream f(path, std::ios::app);
   if (f)
     f << key << " " << t.i_per_lane << " " << t.sum_tile << " " << t.chunk_pairs_log2 << " " << t.grid_per_cu << " "
-      << t.graph_steps << " " << t.symmetric << " " << t.far_split << " " << t.sym_split << " " << t.fused << "\n";
+      << t.graph_steps << " " << t.symmetric << " " << t.far_split << " " << t.sym_split << " " << t.fused << " "
+      << t.sym_rounds << "\n";
 }
 
 // Time of one field evaluation: the pair stage (the sort, the pair-sum
@@ -1207,6 +1240,11 @@ pp_status autotune(pp_ctx* c) {
       for (int sp : {1, 2, 4}) {
         pp_tuning t = best;
         t.sym_split = sp;
+        if ((s = trial(t)) != PP_OK) return s;
+      }
+      for (int sr : {1, 2, 4, 8}) {
+        pp_tuning t = best;
+        t.sym_rounds = sr;
         if ((s = trial(t)) != PP_OK) return s;
       }
     }

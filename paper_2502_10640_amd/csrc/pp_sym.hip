@@ -14,10 +14,13 @@
 // (ds_bpermute, an explicit cross-lane move), so after the group's 64 steps
 // each partial is back at its source's home lane (lane l owns source l): a
 // plain FP32 sum of the wave's 64 K terms for that source.  The 8 waves'
-// partials are then added in wave order with two-sum and stored as the
-// source-side partial (S, C) of the item.  The receiver side is a plain FP32
-// sum over each group of 64 sources, two-summed into registers, and stored as
-// the receiver-side partial at the end of the item.  Worst-case bounds of the
+// partials are then added in wave order with two-sum and stored, rounded
+// once to fl(S + C), as the source-side partial of the item for that round.
+// The receiver side is a plain FP32 sum over each group of 64 sources,
+// two-summed into registers across the item's rounds (sym_rounds of them for
+// large bunches: one receiver block in registers meets the source blocks of
+// consecutive rounds), and stored, rounded once, as the receiver-side partial
+// at the end of the item.  Worst-case bounds of the
 // plain sums: 63 u of the terms' magnitudes on the receiver side (64 terms),
 // (64 K - 1) u on the source side (64 K terms: 255 u at K = 4); errors of
 // random sign grow as the square root of the count (measured at most 6e-7 of
@@ -147,11 +150,11 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
   const int64_t off = B.off;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   constexpr int BS = SYM_WAVES * 64 * K;
-  const int ibase = it.I * BS, jbase0 = it.J * BS;
+  const int ibase = it.I * BS;
+  const int nbk = (n + BS - 1) / BS;
   const float eps2 = B.eps2s;
   const int64_t rho = it.r - a.r0;
   float* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
-  float* sslot = a.slot + ((rho * a.nbt + B.bbase + it.J) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
 
   // near/far split: this wavefront's receiver box (the union of the boxes of
   // its K groups of 64 sorted receivers) and the threshold; the far/near
@@ -207,9 +210,18 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     Sip[k] = Cip[k] = 0.f;
   }
 
-  // this item's part of source block J: groups [g0, g1) of its BS / 64
+  // this item's part of each of its source blocks J: groups [g0, g1) of
+  // the block's BS / 64; rounds d0 .. d0 + nr - 1, the receiver side summed
+  // over all of them
   const int gpart = BS / 64 / a.split;
-  const int g0 = (it.r % a.split) * gpart, g1 = g0 + gpart;
+  const int hpart = it.r % a.split, d0 = it.r / a.split;
+  const int g0 = hpart * gpart, g1 = g0 + gpart;
+  const int nr = DIAG ? 1 : it.nr;
+  for (int kr = 0; kr < nr; ++kr) {
+  const int jblk = DIAG ? it.I : (it.I + d0 + kr) % nbk;
+  const int jbase0 = jblk * BS;
+  const int64_t rho_s = (int64_t)(d0 + kr) * a.split + hpart - a.r0;
+  float* sslot = a.slot + ((rho_s * a.nbt + B.bbase + jblk) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
   for (int g = g0; g < g1; ++g) {
     const int jg = jbase0 + g * 64;
     __syncthreads();  // LDS of the previous group is free
@@ -278,11 +290,11 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
         for (int ww = 1; ww < SYM_WAVES; ++ww) two_sum(S, C, xw[ww][q][l]);
         if (jg + l < n) {
           const int o = g * 64 + l;
-          sslot[(q < 3 ? q : 6) * BS + o] = S;
-          sslot[(q < 3 ? 3 + q : 7) * BS + o] = C;
+          sslot[q * BS + o] = S + C;
         }
       }
     }
+  }
   }
 
   // receiver-side partial
@@ -291,13 +303,9 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
     const int o = (w * K + k) * 64 + l;
     if (ibase + o >= n) continue;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      rslot[c * BS + o] = Si[c][k];
-      rslot[(3 + c) * BS + o] = Ci[c][k];
-    }
+    for (int c = 0; c < 3; ++c) rslot[c * BS + o] = Si[c][k] + Ci[c][k];
     if (PHI) {
-      rslot[6 * BS + o] = Sip[k];
-      rslot[7 * BS + o] = Cip[k];
+      rslot[3 * BS + o] = Sip[k] + Cip[k];
     }
   }
 }
@@ -358,6 +366,7 @@ __global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
   }
   const int64_t sl = (int64_t)SLOT_PLANES * BS;
   const int S = a.split, part = o / (BS / S);
+  const int M = sym_rounds_for(nbk, a.rounds);
   for (int v = a.r0; v < a.r1; ++v) {
     const float* base = a.slot + ((int64_t)(v - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
     const int r = v / S;
@@ -365,31 +374,33 @@ __global__ __launch_bounds__(256) void sym_fold_kernel(SymFoldArgs a) {
       if (v == 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          rs[q] = base[(q < 3 ? q : 6) * BS];
-          rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+          rs[q] = base[q * BS];
+          rc[q] = 0.f;
         }
       } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          two_sum_pair(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+          two_sum(rs[q], rc[q], base[q * BS]);
       }
       continue;
     }
     if (r > half) continue;  // the bunch has no item in this round
-    // receiver side: item (X, X + r); source side: item (X - r, X).  With an
-    // even block count the round r = nbk / 2 holds only the items with I < nbk / 2.
-    const bool has_r = !(2 * r == nbk && X >= half);
+    // receiver side: the item of block X whose group of M rounds starts at
+    // round r (one slot for the group); source side: item (X - r, X) of round
+    // r.  With an even block count the round r = nbk / 2 holds only the items
+    // with I < nbk / 2.
+    const bool has_r = (r - 1) % M == 0 && sym_group_rounds(nbk, M, r, X) > 0;
     const int js = X - r < 0 ? X - r + nbk : X - r;
     const bool has_s = !(2 * r == nbk && js >= half) && v % S == part;
     if (has_r) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        two_sum_pair(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+        two_sum(rs[q], rc[q], base[q * BS]);
     }
     if (has_s) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        two_sum_pair(ss[q], sc[q], base[sl + (q < 3 ? q : 6) * BS], base[sl + (q < 3 ? 3 + q : 7) * BS]);
+        two_sum(ss[q], sc[q], base[sl + q * BS]);
     }
   }
 #pragma unroll

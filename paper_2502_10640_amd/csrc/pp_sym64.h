@@ -29,6 +29,7 @@ struct SymFoldArgs64 {
   int32_t nbt;
   int32_t block_size;
   int32_t split;
+  int32_t rounds;          // the sym_rounds tuning value
 };
 
 // Wavefronts per item; a block is SYM64_WG * i_per_lane particles.  Four

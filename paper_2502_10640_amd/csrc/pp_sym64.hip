@@ -10,8 +10,10 @@
 // ds_bpermute per double), arriving at the source's home lane after the 64th
 // step.  r^-3 comes from v_rsq_f64 and one third-order series correction
 // (inv_r3_64).  Items write FP64 partial slots indexed (sub-round, block,
-// side); the fold adds them in sub-round order, so every addition has a fixed
-// order.  A sub-round r S + h is part h of round r when block pairs are split
+// side), one value per component rounded once from the item's compensated
+// sum, a source-side slot per round and one receiver-side slot per item (an
+// item covers sym_rounds consecutive rounds in large bunches); the fold adds
+// them in sub-round order, so every addition has a fixed order.  A sub-round r S + h is part h of round r when block pairs are split
 // in S parts of the source block's groups (S = 1: plain rounds).
 //
 // Positions are the unscaled FP64 state and separations are plain FP64
@@ -43,11 +45,6 @@ __device__ __forceinline__ double lane_read64(double v, int src_lane) {
   const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(bits & 0xffffffffll));
   const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(bits >> 32));
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ __forceinline__ void two_sum_pair64(double& s, double& c, double t, double tc) {
-  two_sum(s, c, t);
-  c += tc;
 }
 
 template <int K, bool UQ, bool PHI, bool DIAG>
@@ -116,13 +113,12 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
   const int64_t off = B.off;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   constexpr int BS = SYM64_WAVES * 64 * K;
-  const int ibase = it.I * BS, jbase0 = it.J * BS;
-  const bool pad = (n - ibase < BS) || (n - jbase0 < BS);  // a ragged last block takes part
+  const int ibase = it.I * BS;
+  const int nbk = (n + BS - 1) / BS;
   const SeriesConst sc = series_const();  // series constants held in registers
   const double eps2 = B.eps2;
   const int64_t rho = it.r - a.r0;
   double* rslot = a.slot + ((rho * a.nbt + B.bbase + it.I) * 2) * (int64_t)(SLOT_PLANES * BS);
-  double* sslot = a.slot + ((rho * a.nbt + B.bbase + it.J) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
 
   double xi[K], yi[K], zi[K], qi[K];
   double Si[3][K], Ci[3][K], Sip[K], Cip[K];
@@ -142,9 +138,19 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     Sip[k] = Cip[k] = 0.0;
   }
 
-  // this item's part of source block J: groups [g0, g1) of its BS / 64
+  // this item's part of each of its source blocks J: groups [g0, g1) of
+  // the block's BS / 64; rounds d0 .. d0 + nr - 1, the receiver side summed
+  // over all of them
   const int gpart = BS / 64 / a.split;
-  const int g0 = (it.r % a.split) * gpart, g1 = g0 + gpart;
+  const int hpart = it.r % a.split, d0 = it.r / a.split;
+  const int g0 = hpart * gpart, g1 = g0 + gpart;
+  const int nr = DIAG ? 1 : it.nr;
+  for (int kr = 0; kr < nr; ++kr) {
+  const int jblk = DIAG ? it.I : (it.I + d0 + kr) % nbk;
+  const int jbase0 = jblk * BS;
+  const bool pad = (n - ibase < BS) || (n - jbase0 < BS);  // a ragged last block takes part
+  const int64_t rho_s = (int64_t)(d0 + kr) * a.split + hpart - a.r0;
+  double* sslot = a.slot + ((rho_s * a.nbt + B.bbase + jblk) * 2 + 1) * (int64_t)(SLOT_PLANES * BS);
   for (int g = g0; g < g1; ++g) {
     const int jg = jbase0 + g * 64;
     __syncthreads();  // LDS of the previous group is free
@@ -190,11 +196,11 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
         for (int ww = 1; ww < SYM64_WAVES; ++ww) two_sum(S, C, xw[ww][q][l]);
         if (jg + l < n) {
           const int o = g * 64 + l;
-          sslot[(q < 3 ? q : 6) * BS + o] = S;
-          sslot[(q < 3 ? 3 + q : 7) * BS + o] = C;
+          sslot[q * BS + o] = S + C;
         }
       }
     }
+  }
   }
 
   // receiver-side partial
@@ -203,13 +209,9 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
     const int o = (w * K + k) * 64 + l;
     if (ibase + o >= n) continue;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      rslot[c * BS + o] = Si[c][k];
-      rslot[(3 + c) * BS + o] = Ci[c][k];
-    }
+    for (int c = 0; c < 3; ++c) rslot[c * BS + o] = Si[c][k] + Ci[c][k];
     if (PHI) {
-      rslot[6 * BS + o] = Sip[k];
-      rslot[7 * BS + o] = Cip[k];
+      rslot[3 * BS + o] = Sip[k] + Cip[k];
     }
   }
 }
@@ -270,6 +272,7 @@ __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
   }
   const int64_t sl = (int64_t)SLOT_PLANES * BS;
   const int S = a.split, part = o / (BS / S);
+  const int M = sym_rounds_for(nbk, a.rounds);
   for (int v = a.r0; v < a.r1; ++v) {
     const double* base = a.slot + ((int64_t)(v - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
     const int r = v / S;
@@ -277,31 +280,33 @@ __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
       if (v == 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          rs[q] = base[(q < 3 ? q : 6) * BS];
-          rc[q] = base[(q < 3 ? 3 + q : 7) * BS];
+          rs[q] = base[q * BS];
+          rc[q] = 0.0;
         }
       } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          two_sum_pair64(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+          two_sum(rs[q], rc[q], base[q * BS]);
       }
       continue;
     }
     if (r > half) continue;  // the bunch has no item in this round
-    // receiver side: item (X, X + r); source side: item (X - r, X); with an even
-    // block count the round r = nbk / 2 holds only the items with I < nbk / 2
-    const bool has_r = !(2 * r == nbk && X >= half);
+    // receiver side: the item of block X whose group of M rounds starts at
+    // round r (one slot for the group); source side: item (X - r, X) of round
+    // r.  With an even block count the round r = nbk / 2 holds only the items
+    // with I < nbk / 2.
+    const bool has_r = (r - 1) % M == 0 && sym_group_rounds(nbk, M, r, X) > 0;
     const int js = X - r < 0 ? X - r + nbk : X - r;
     const bool has_s = !(2 * r == nbk && js >= half) && v % S == part;
     if (has_r) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        two_sum_pair64(rs[q], rc[q], base[(q < 3 ? q : 6) * BS], base[(q < 3 ? 3 + q : 7) * BS]);
+        two_sum(rs[q], rc[q], base[q * BS]);
     }
     if (has_s) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        two_sum_pair64(ss[q], sc[q], base[sl + (q < 3 ? q : 6) * BS], base[sl + (q < 3 ? 3 + q : 7) * BS]);
+        two_sum(ss[q], sc[q], base[sl + q * BS]);
     }
   }
 #pragma unroll

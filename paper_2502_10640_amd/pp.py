@@ -72,7 +72,8 @@ class Diag(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("i_per_lane", ctypes.c_int32), ("sum_tile", ctypes.c_int32), ("chunk_pairs_log2", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("symmetric", ctypes.c_int32),
-                ("far_split", ctypes.c_int32), ("sym_split", ctypes.c_int32), ("fused", ctypes.c_int32)]
+                ("far_split", ctypes.c_int32), ("sym_split", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("sym_rounds", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -420,7 +420,7 @@ def test_full_size_sampled_parity_cold_sphere_1m(orc, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_split_with_many_slot_bands_sampled_parity_1m(orc, prec):
     """Block pairs split in 2 at 1 048 576 particles: the sub-rounds' slots
-    exceed one 8 GiB band (5 bands mixed, 17 FP64), so the fold carries the
+    exceed one 12 GiB band (2 bands mixed, 6 FP64), so the fold carries the
     accumulators across bands and the diagonal items sit in the first one."""
     b = wl.workload("cold_sphere_1m")[0]
     rng = np.random.default_rng(98)
@@ -625,10 +625,10 @@ def test_autotune_keeps_a_passing_tiling_and_caches_it(orc, tmp_path, monkeypatc
     lines = cache.read_text().splitlines()
     assert lines[:2] == junk.splitlines() and len(lines) == 3
     line = lines[2].split()
-    assert len(line) == 10 and line[0].startswith("gfx950:")
+    assert len(line) == 11 and line[0].startswith("gfx950:")
     assert [int(v) for v in line[1:]] == [tuned[k] for k in ("i_per_lane", "sum_tile", "chunk_pairs_log2",
                                                                "grid_per_cu", "graph_steps", "symmetric",
-                                                               "far_split", "sym_split", "fused")]
+                                                               "far_split", "sym_split", "fused", "sym_rounds")]
     with Sim([b], "mixed") as sim:
         sim.step_batched(1, graph=False, autotune=True)
         assert sim.tuning() == tuned
@@ -849,3 +849,74 @@ def test_simulation_calls_under_another_current_stream(orc, gpu):
             sim.sync()
             got = {k: v.cpu().numpy() for k, v in f.items()}
     check_field(got, oracle_field(orc, b), TOL["mixed"], "under another stream")
+
+
+# ---------------------------------------------------------------------------
+# several rounds per symmetric item (tuning field sym_rounds)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,M", [("mixed", 2), ("mixed", 4), ("fp64", 4), ("fp64", 8)])
+def test_sym_rounds_field_parity(orc, prec, M):
+    """Items sweeping M consecutive rounds (one receiver-side partial per
+    group of rounds): a 70000-particle bunch (137 blocks mixed, 274 FP64 at
+    one receiver per lane, so the groups apply: at least 32 M blocks), a
+    small one that keeps one round per item, and a 5-particle one in one
+    batch; sampled receivers of the large bunch and every receiver of the
+    others against the oracle."""
+    big = wl.workload("gaussian_65536", n_override=70000)[0]
+    bunches = [big, wl.workload("cold_sphere_2048", n_override=3000)[0],
+               wl.workload("cold_sphere_2048", n_override=5)[0]]
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "sym_split": 1, "sym_rounds": M,
+           "far_split": 3 if prec == "mixed" else 0}
+    say(f"sym_rounds={M} field {prec} sizes={[b.n for b in bunches]}")
+    rng = np.random.default_rng(31)
+    recv = np.sort(rng.choice(big.n, 256, replace=False))
+    with Sim(bunches, prec, tuning=tun) as sim:
+        assert sim.tuning()["sym_rounds"] == M
+        full = gpu_field(sim)
+        slices = [sim.bunch_slice(k) for k in range(len(bunches))]
+    got = {key: v[slices[0]][recv] for key, v in full.items()}
+    check_field(got, oracle_field(orc, big, recv=recv), TOL[prec], f"sym_rounds={M} n={big.n} sampled")
+    for k, b in enumerate(bunches[1:], start=1):
+        check_field({key: v[slices[k]] for key, v in full.items()}, oracle_field(orc, b), TOL[prec],
+                    f"sym_rounds={M} n={b.n}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_sym_rounds_bitwise_equivalences(prec):
+    """With 4 rounds per item: push == step_batched with graphs, and a batch
+    (one bunch with the groups, one without) equals the bunches alone."""
+    bunches = [wl.workload("gaussian_65536", n_override=70000)[0], wl.workload("gaussian_65536", n_override=2500)[0]]
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "sym_split": 1, "sym_rounds": 4, "graph_steps": 2,
+           "far_split": 3 if prec == "mixed" else 0}
+    say(f"sym_rounds=4 push == graph, batch == alone, {prec}")
+    res = []
+    for mode in ("push", "graph"):
+        with Sim(bunches, prec, tuning=tun) as sim:
+            if mode == "push":
+                sim.push(4)
+            else:
+                sim.step_batched(4, graph=True)
+            res.append([np.concatenate([sim.host(k)[sim.bunch_slice(i)] for k in ("x", "vx", "vz")])
+                        for i in range(len(bunches))])
+    for i in range(len(bunches)):
+        np.testing.assert_array_equal(res[0][i], res[1][i])
+        with Sim([bunches[i]], prec, tuning=tun) as one:
+            one.push(4)
+            alone = np.concatenate([one.host(k) for k in ("x", "vx", "vz")])
+        np.testing.assert_array_equal(res[0][i], alone)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_sym_rounds_with_split_and_bands_sampled_parity_1m(orc, prec):
+    """8 rounds per item at 1 048 576 particles with block pairs split in 2:
+    the groups of rounds line up with the slot bands (2 mixed, 6 FP64)."""
+    b = wl.workload("cold_sphere_1m")[0]
+    rng = np.random.default_rng(97)
+    recv = np.sort(rng.choice(b.n, 256, replace=False))
+    tun = {"symmetric": 1, "fused": 0, "i_per_lane": 4, "sym_split": 2, "sym_rounds": 8,
+           "far_split": 3 if prec == "mixed" else 0}
+    say(f"sym_rounds=8 split 2 with slot bands, cold_sphere_1m {prec}")
+    with Sim([b], prec, tuning=tun) as sim:
+        got = gpu_field(sim, sl=recv)
+    check_field(got, oracle_field(orc, b, recv=recv), TOL[prec], f"cold_sphere_1m/{prec} sym_rounds 8 split 2")
