@@ -264,18 +264,9 @@ def step_times(a):
 
 
 def total_energy(sim):
-    """Total energy per bunch: kinetic from the state, potential from the GPU's
-    softened potential (pp_field with phi); the sums are done here in FP64."""
-    import numpy as np
-    f = sim.field(want_phi=True)
-    phi = f["phi"].cpu().numpy()
-    v2 = sim.host("vx") ** 2 + sim.host("vy") ** 2 + sim.host("vz") ** 2
-    q, m = sim.host("q"), sim.host("m")
-    out = []
-    for k, b in enumerate(sim.bunches):
-        sl = sim.bunch_slice(k)
-        out.append(0.5 * b.weight * float(np.sum(m[sl] * v2[sl])) + 0.5 * b.weight * float(np.sum(q[sl] * phi[sl])))
-    return out
+    """Total energy per bunch (kinetic + softened potential, Sec. 2.2) from
+    pp_diagnostics: the library's FP64 reductions on the device."""
+    return [d["total"] for d in sim.diagnostics()]
 
 
 def drift(a):
