@@ -1043,7 +1043,10 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
     t.far_split = 0;
     t.sym_split = 1;
     t.fused = (int32_t)R;
-    t.i_per_lane = 2;
+    // workgroups of 512 threads; FP64 from 16 receivers per workgroup on
+    // 1024 (`bench.py --mode steps`: 16.9 -> 16.3 us at 4096 particles,
+    // 50.6 -> 48.5 us at 8192; at 2048 and in mixed precision 512 is faster)
+    t.i_per_lane = (!mixed && R >= 16) ? 4 : 2;
   }
   return t;
 }

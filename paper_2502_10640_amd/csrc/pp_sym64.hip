@@ -21,6 +21,7 @@
 // precision).
 #include "pp_device.h"
 #include "pp_device64.h"
+#include "pp_fold.h"
 #include "pp_sym64.h"
 
 #include <cmath>
@@ -242,9 +243,11 @@ hipError_t go_sym64_k(const SymArgs64& a, int32_t first, int32_t count, bool uq,
 // the accumulators; sub-round 0 (the first part of the diagonal items) starts
 // them.  Receiver side: every part of a block pair; source side: only the part
 // that holds this position.
-template <bool PHI>
+// One thread per (particle, component): grid y is the component (x, y, z,
+// and the potential when asked for); each component's sums are independent.
 __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
   if (p >= a.n_total) return;
   const int b = a.bid[p];
   if (b < 0) return;
@@ -252,70 +255,27 @@ __global__ __launch_bounds__(256) void sym64_fold_kernel(SymFoldArgs64 a) {
   const int BS = a.block_size;
   const int l = (int)(p - B.off);
   const int X = l / BS, o = l - X * BS;
-  const int nbk = (int)((B.n + BS - 1) / BS), half = nbk / 2;
-  constexpr int NQ = PHI ? 4 : 3;
+  const int nbk = (int)((B.n + BS - 1) / BS);
   const int64_t P = a.n_total;
-  double rs[NQ], rc[NQ], ss[NQ], sc[NQ];
   // accumulator planes of component q: receiver S, C and source S, C
-  auto pl = [](int q, int k) { return q < 3 ? q + 3 * k : 12 + k; };
-  if (a.r0 == 0) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) rs[q] = rc[q] = ss[q] = sc[q] = 0.0;
-  } else {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      rs[q] = a.acc[pl(q, 0) * P + p];
-      rc[q] = a.acc[pl(q, 1) * P + p];
-      ss[q] = a.acc[pl(q, 2) * P + p];
-      sc[q] = a.acc[pl(q, 3) * P + p];
-    }
+  const int pl = q < 3 ? q : 12;
+  const int ps = q < 3 ? 3 : 1;
+  double rs = 0, rc = 0, ss = 0, sc = 0;
+  if (a.r0 != 0) {
+    rs = a.acc[(pl + 0 * ps) * P + p];
+    rc = a.acc[(pl + 1 * ps) * P + p];
+    ss = a.acc[(pl + 2 * ps) * P + p];
+    sc = a.acc[(pl + 3 * ps) * P + p];
   }
   const int64_t sl = (int64_t)SLOT_PLANES * BS;
   const int S = a.split, part = o / (BS / S);
   const int M = sym_rounds_for(nbk, a.rounds);
-  for (int v = a.r0; v < a.r1; ++v) {
-    const double* base = a.slot + ((int64_t)(v - a.r0) * a.nbt + B.bbase + X) * 2 * sl + o;
-    const int r = v / S;
-    if (r == 0) {
-      if (v == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          rs[q] = base[q * BS];
-          rc[q] = 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          two_sum(rs[q], rc[q], base[q * BS]);
-      }
-      continue;
-    }
-    if (r > half) continue;  // the bunch has no item in this round
-    // receiver side: the item of block X whose group of M rounds starts at
-    // round r (one slot for the group); source side: item (X - r, X) of round
-    // r.  With an even block count the round r = nbk / 2 holds only the items
-    // with I < nbk / 2.
-    const bool has_r = (r - 1) % M == 0 && sym_group_rounds(nbk, M, r, X) > 0;
-    const int js = X - r < 0 ? X - r + nbk : X - r;
-    const bool has_s = !(2 * r == nbk && js >= half) && v % S == part;
-    if (has_r) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        two_sum(rs[q], rc[q], base[q * BS]);
-    }
-    if (has_s) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        two_sum(ss[q], sc[q], base[sl + q * BS]);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    a.acc[pl(q, 0) * P + p] = rs[q];
-    a.acc[pl(q, 1) * P + p] = rc[q];
-    a.acc[pl(q, 2) * P + p] = ss[q];
-    a.acc[pl(q, 3) * P + p] = sc[q];
-  }
+  fold_sweep<double>(a.slot + ((int64_t)B.bbase + X) * 2 * sl + (int64_t)q * BS + o, (int64_t)a.nbt * 2 * sl, sl, a.r0,
+                  a.r1, ilog2_pow2(S), part, nbk, ilog2_pow2(M), X, rs, rc, ss, sc);
+  a.acc[(pl + 0 * ps) * P + p] = rs;
+  a.acc[(pl + 1 * ps) * P + p] = rc;
+  a.acc[(pl + 2 * ps) * P + p] = ss;
+  a.acc[(pl + 3 * ps) * P + p] = sc;
 }
 
 }  // namespace
@@ -335,9 +295,9 @@ int sym64_blocks_per_cu(int i_per_lane) {
 hipError_t launch_sym64_fold(const SymFoldArgs64& a, bool with_phi, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_total + 255) / 256);
   if (with_phi)
-    hipLaunchKernelGGL(sym64_fold_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sym64_fold_kernel, dim3(grid, 4), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(sym64_fold_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sym64_fold_kernel, dim3(grid, 3), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
