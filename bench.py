@@ -183,13 +183,14 @@ def tilings(a):
 
 UBENCH_OPS = {  # name: (op code, lane operations per chain-iteration, iterations)
     "fma_f32": (0, 1, 400000), "add_f32": (1, 1, 400000), "mul_f32": (2, 1, 400000),
-    "rsq_f32": (3, 1, 100000), "fma8_rsq_f32": (4, 9, 40000), "fma_f64": (5, 1, 200000)}
+    "rsq_f32": (3, 1, 100000), "fma8_rsq_f32": (4, 9, 40000), "fma_f64": (5, 1, 200000),
+    "add_f64": (6, 1, 200000), "mul_f64": (7, 1, 200000), "rsq_f64": (8, 1, 50000)}
 
 
 def ubench(a):
     """Vector-ALU issue rates of gfx950 (libpp_ubench.so): lane operations per
     shader clock per compute unit for FP32 FMA, add, mul, v_rsq_f32, 8 FMA
-    interleaved with one rsq, and FP64 FMA.  8 workgroups of 256 threads per
+    interleaved with one rsq, and FP64 FMA, add, mul and v_rsq_f64.  8 workgroups of 256 threads per
     CU, 8 independent chains per thread; the clock is measured inside the
     kernel (shader-clock counter against the wall clock)."""
     import ctypes

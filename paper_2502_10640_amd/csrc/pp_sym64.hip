@@ -190,7 +190,7 @@ __device__ void sym_item64(const SymArgs64& a, const SymItem& it, SymShared64& s
       for (int q = 0; q < (PHI ? 4 : 3); ++q) xw[w][q][l] = aj[q];
       __syncthreads();
       // one thread per (source, component): waves 0-3 add the waves' partials
-      // in wave order with two-sum and store the source-side (S, C)
+      // in wave order with two-sum and store the source-side partial, S + C
       const int q = tid >> 6;
       if (q < (PHI ? 4 : 3)) {
         double S = xw[0][q][l], C = 0.0;

@@ -5,7 +5,7 @@
 // They measure what the pair kernels' issue model needs: how many FP32 lane
 // operations a compute unit completes per shader clock for FMA, add, mul and
 // v_rsq_f32 alone, for FMA and rsq streams interleaved (as in a pair
-// evaluation), and for FP64 FMA.  Each thread runs 8 independent dependence
+// evaluation), and the same for FP64 FMA, add, mul and v_rsq_f64.  Each thread runs 8 independent dependence
 // chains so that issue, not latency, limits the rate; the grid is 8
 // workgroups of 256 threads per CU.  Every chain's result is stored, so the
 // compiler cannot drop the work.  The shader clock during the kernel is read
@@ -20,7 +20,10 @@ namespace {
 constexpr int kChains = 8;
 constexpr int kThreads = 256;
 
-enum Op : int32_t { OP_FMA = 0, OP_ADD = 1, OP_MUL = 2, OP_RSQ = 3, OP_FMA_RSQ = 4, OP_FMA64 = 5 };
+enum Op : int32_t {
+  OP_FMA = 0, OP_ADD = 1, OP_MUL = 2, OP_RSQ = 3, OP_FMA_RSQ = 4,
+  OP_FMA64 = 5, OP_ADD64 = 6, OP_MUL64 = 7, OP_RSQ64 = 8
+};
 
 // ops[] holds per-thread inputs; out[] receives the chains' results; clk[2 *
 // block] the block's shader-clock and real-time spans (thread 0).
@@ -29,14 +32,19 @@ __global__ __launch_bounds__(kThreads) void valu_kernel(const float* in, float* 
                                                         unsigned long long* clk) {
   const int t = blockIdx.x * kThreads + threadIdx.x;
   const unsigned long long c0 = clock64(), r0 = wall_clock64();
-  if (OP == OP_FMA64) {
+  if (OP >= OP_FMA64) {
     double a[kChains];
     const double m = 1.0 + 1e-9 * in[t & 1023], c = 1e-7;
 #pragma unroll
-    for (int k = 0; k < kChains; ++k) a[k] = (double)in[(t + k) & 1023];
+    for (int k = 0; k < kChains; ++k) a[k] = 1.0 + (double)in[(t + k) & 1023];
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
-      for (int k = 0; k < kChains; ++k) a[k] = fma(a[k], m, c);
+      for (int k = 0; k < kChains; ++k) {
+        if (OP == OP_FMA64) a[k] = fma(a[k], m, c);
+        if (OP == OP_ADD64) a[k] = a[k] + c;
+        if (OP == OP_MUL64) a[k] = a[k] * m;
+        if (OP == OP_RSQ64) a[k] = __builtin_amdgcn_rsq(a[k]);
+      }
     }
     double s = 0.0;
 #pragma unroll
@@ -101,6 +109,15 @@ extern "C" int pp_ubench_valu(int op, int blocks, int iters, const float* in, fl
       break;
     case OP_FMA64:
       hipLaunchKernelGGL(valu_kernel<OP_FMA64>, dim3(blocks), dim3(kThreads), 0, nullptr, in, out, iters, clk);
+      break;
+    case OP_ADD64:
+      hipLaunchKernelGGL(valu_kernel<OP_ADD64>, dim3(blocks), dim3(kThreads), 0, nullptr, in, out, iters, clk);
+      break;
+    case OP_MUL64:
+      hipLaunchKernelGGL(valu_kernel<OP_MUL64>, dim3(blocks), dim3(kThreads), 0, nullptr, in, out, iters, clk);
+      break;
+    case OP_RSQ64:
+      hipLaunchKernelGGL(valu_kernel<OP_RSQ64>, dim3(blocks), dim3(kThreads), 0, nullptr, in, out, iters, clk);
       break;
     default:
       (void)hipEventDestroy(e0);
