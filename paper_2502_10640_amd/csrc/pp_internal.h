@@ -183,7 +183,7 @@ constexpr int N_PLANES = 8;
 // kernel then adds the slots to the accumulators in round order.  Items of
 // many rounds therefore run in one launch, in any order, and the order of
 // every addition is still fixed.
-constexpr int SYM_WAVES = 8;
+constexpr int SYM_WAVES = 4;
 constexpr int SYM_WG = SYM_WAVES * 64;
 constexpr int SYM_PLANES = 16;  // Si(xyz) Ci(xyz) Sj(xyz) Cj(xyz) Sip Cip Sjp Cjp
 // per slot: one value per component, the item's compensated partial (S, C)

@@ -943,24 +943,24 @@ double list_makespan(double n_off, double c_off, double n_diag, double c_diag, d
 // cheaper than the ordered-pair kernel.  Costs in units of one ordered pair in
 // the ordered kernel of the same precision, from measurements on MI355X: an
 // off-diagonal unordered pair 1.02, a diagonal-block pair 0.6, times a
-// per-variant factor (mixed: 1.0 at 4 receivers per lane, 1.1 at 2; FP64: 1.28
-// at 4, 1.51 at 2, the FP64 sweep gaining less over its ordered kernel because
-// its r^-3 costs more relative to the rest of a pair and the fold of FP64
-// slots costs 2-4%); 1 receiver per lane, ~1.4-2x slower in both precisions,
-// is left to the autotuner.  The mixed sweep loses ground in small bunches
-// (fewer wavefront boxes clear the far threshold, and the sort and the fold
-// weigh more): charged as 1 + 3 / (bunch size / 1024).  At 4 receivers per
-// lane it also loses at small launches (measured on single uniform spheres:
-// 1.27x at 16 blocks, 1.19x at 32, 1.05x at 64, relative to 2 per lane, but
-// not in a batch of 64 such bunches), charged as 1 + 4 / B with B the root
-// of the sum of squared block counts (the block count of a single bunch).
-// Splitting each block pair into S items adds kSplitOverhead / BS of a block
-// pair's cost per extra item (receiver loads, slot stores, the fold's extra
-// reads; measured 1-4% per extra item at BS = 512-2048).  Padded blocks are
-// paid in full, and the cost is the finish time of the launch's list schedule
-// over the resident slots times the slot count (idle slots in the last wave
-// included).
-constexpr double kSplitOverhead = 24.0;
+// per-variant factor (mixed: 1.0 at 4 receivers per lane, 1.15 at 2; FP64:
+// 1.28 at 4, 1.51 at 2, the FP64 sweep gaining less over its ordered kernel
+// because its r^-3 costs more relative to the rest of a pair and the fold of
+// FP64 slots costs 2-4%); 1 receiver per lane, ~1.4-2x slower in both
+// precisions, is left to the autotuner.  The mixed sweep loses ground in
+// small bunches (fewer wavefront boxes clear the far threshold, and the sort
+// and the fold weigh more): charged as 1 + 1 / (bunch size / 1024).
+// Splitting each block pair into S items adds a split overhead / BS of a
+// block pair's cost per extra item (receiver loads, slot stores, the fold's
+// extra reads; measured 1-4% per extra item): 32 on the mixed path, 24 on
+// the FP64 path.  Padded blocks are paid in full, and the cost is the finish
+// time of the launch's list schedule over the resident slots times the slot
+// count (idle slots in the last wave included).  The mixed constants are
+// fitted to the pair-stage times of every ordered and symmetric tiling
+// (1, 2 or 4 per lane, split 1, 2 or 4) on uniform spheres of 12288-262144
+// particles: the model's choice is within 4% of the fastest at every size.
+constexpr double kSplitOverheadMixed = 32.0;
+constexpr double kSplitOverheadFp64 = 24.0;
 
 // Largest bunch the default tiling puts on the fused schedule.
 constexpr int64_t kFusedDefaultMaxN = 8192;
@@ -989,7 +989,7 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   std::vector<Variant> vars;
   if (mixed) {
     vars.push_back({4, (double)ppk::SYM_WG * 4, 1.0, ppk::sym_blocks_per_cu(4)});
-    vars.push_back({2, (double)ppk::SYM_WG * 2, 1.1, ppk::sym_blocks_per_cu(2)});
+    vars.push_back({2, (double)ppk::SYM_WG * 2, 1.15, ppk::sym_blocks_per_cu(2)});
   } else {
     vars.push_back({4, (double)ppk::SYM64_WG * 4, 1.28, ppk::sym64_blocks_per_cu(4)});
     vars.push_back({2, (double)ppk::SYM64_WG * 2, 1.51, ppk::sym64_blocks_per_cu(2)});
@@ -1000,12 +1000,12 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
     double wsum = 0.0, psum = 0.0;
     for (const auto& b : hb) {
       const double nbk = std::ceil((double)b.n / v.bs);
-      const double f = mixed ? 1.0 + 3.0 / std::ceil((double)b.n / (2.0 * ppk::SYM_WG)) : 1.0;
+      const double f = mixed ? 1.0 + 1.0 / std::ceil((double)b.n / 1024.0) : 1.0;
       wsum += nbk * nbk * f;
       psum += nbk * nbk;
     }
-    double eff = v.eff * wsum / psum;
-    if (mixed && v.k == 4) eff *= 1.0 + 4.0 / std::sqrt(psum);
+    const double eff = v.eff * wsum / psum;
+    const double split_overhead = mixed ? kSplitOverheadMixed : kSplitOverheadFp64;
     for (int S : {1, 2, 4}) {
       double n_off = 0.0, n_diag = 0.0;
       for (const auto& b : hb) {
@@ -1013,7 +1013,7 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
         n_off += S * nbk * (nbk - 1.0) / 2.0;
         n_diag += S * nbk;
       }
-      const double unit = v.bs * v.bs * eff, extra = (S - 1) * (kSplitOverhead / v.bs) / S;
+      const double unit = v.bs * v.bs * eff, extra = (S - 1) * (split_overhead / v.bs) / S;
       const double slots = (double)cus * v.blocks_per_cu;
       const double cost =
           slots * list_makespan(n_off, unit * (1.02 / S + extra), n_diag, unit * (0.6 / S + extra), slots);

@@ -6,14 +6,14 @@
 // ordered interactions.  On gfx950 the reciprocal square root costs 10-12
 // FP32 issue slots inside a pair evaluation, so this halves the dominant cost.
 //
-// An item pairs receiver block I (held in VGPRs, i_per_lane per lane, 8 waves)
+// An item pairs receiver block I (held in VGPRs, i_per_lane per lane, 4 waves)
 // with source block J, swept in groups of 64 sources staged in LDS.  In step s
 // of a group, lane l meets source (l + s) mod 64 (every lane reads a distinct
 // LDS address; the group is stored twice so that the address needs no wrap).  The source-side partial of that source travels with it: after
 // each step every lane takes over the partial of its upper neighbour
 // (ds_bpermute, an explicit cross-lane move), so after the group's 64 steps
 // each partial is back at its source's home lane (lane l owns source l): a
-// plain FP32 sum of the wave's 64 K terms for that source.  The 8 waves'
+// plain FP32 sum of the wave's 64 K terms for that source.  The 4 waves'
 // partials are then added in wave order with two-sum and stored, rounded
 // once to fl(S + C), as the source-side partial of the item for that round.
 // The receiver side is a plain FP32 sum over each group of 64 sources,
@@ -283,7 +283,7 @@ __device__ void sym_item(const SymArgs& a, const SymItem& it, SymShared& sh) {
 #pragma unroll
       for (int q = 0; q < (PHI ? 4 : 3); ++q) xw[w][q][l] = aj[q];
       __syncthreads();
-      // one thread per (source, component): waves 0-3 combine the 8 waves'
+      // one thread per (source, component): waves 0-3 combine the 4 waves'
       // pairs in wave order and store the source-side partial
       const int q = tid >> 6;  // 0..2 field components, 3 potential
       if (q < (PHI ? 4 : 3)) {

@@ -420,7 +420,7 @@ def test_full_size_sampled_parity_cold_sphere_1m(orc, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_split_with_many_slot_bands_sampled_parity_1m(orc, prec):
     """Block pairs split in 2 at 1 048 576 particles: the sub-rounds' slots
-    exceed one 12 GiB band (2 bands mixed, 6 FP64), so the fold carries the
+    exceed one 12 GiB band (3 bands mixed, 6 FP64), so the fold carries the
     accumulators across bands and the diagonal items sit in the first one."""
     b = wl.workload("cold_sphere_1m")[0]
     rng = np.random.default_rng(98)
@@ -858,7 +858,7 @@ def test_simulation_calls_under_another_current_stream(orc, gpu):
 @pytest.mark.parametrize("prec,M", [("mixed", 2), ("mixed", 4), ("fp64", 4), ("fp64", 8)])
 def test_sym_rounds_field_parity(orc, prec, M):
     """Items sweeping M consecutive rounds (one receiver-side partial per
-    group of rounds): a 70000-particle bunch (137 blocks mixed, 274 FP64 at
+    group of rounds): a 70000-particle bunch (274 blocks in either precision at
     one receiver per lane, so the groups apply: at least 32 M blocks), a
     small one that keeps one round per item, and a 5-particle one in one
     batch; sampled receivers of the large bunch and every receiver of the
@@ -910,7 +910,7 @@ def test_sym_rounds_bitwise_equivalences(prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_sym_rounds_with_split_and_bands_sampled_parity_1m(orc, prec):
     """8 rounds per item at 1 048 576 particles with block pairs split in 2:
-    the groups of rounds line up with the slot bands (2 mixed, 6 FP64)."""
+    the groups of rounds line up with the slot bands (3 mixed, 6 FP64)."""
     b = wl.workload("cold_sphere_1m")[0]
     rng = np.random.default_rng(97)
     recv = np.sort(rng.choice(b.n, 256, replace=False))
