@@ -174,9 +174,10 @@ typedef struct {
                             through LDS, and applies the update itself, so a
                             step is one kernel.  Changes the order of
                             additions, hence the bits.                          */
-  int32_t sym_rounds;    /* symmetric only: 1, 2, 4 or 8 consecutive rounds per
-                            item for bunches of at least 32 x sym_rounds
-                            blocks (others: 1).  An item then keeps its
+  int32_t sym_rounds;    /* symmetric only: up to 1, 2, 4 or 8 consecutive
+                            rounds per item: a bunch takes the largest power
+                            of two M <= sym_rounds with at least 128 M
+                            blocks (else 1).  An item then keeps its
                             receiver block in registers across that many
                             source blocks: one receiver-side partial instead
                             of one per round, and the receiver block read once

@@ -205,12 +205,17 @@ struct SymItem {
 };
 
 // Receiver-side rounds per item of a bunch of nbk blocks for the tuning value
-// sym_rounds (1, 2, 4 or 8): the value where the bunch has at least
-// 32 sym_rounds blocks, else 1 (mid-size bunches keep every item short, so
-// that the last wave of items stays full).  Groups of rounds start at rounds
-// 1, 1 + M, 1 + 2 M, ...; depends only on the bunch's size and the tuning.
+// sym_rounds (1, 2, 4 or 8): the largest power of two M <= sym_rounds with at
+// least 128 M blocks (smaller bunches keep their items short, so that the
+// last wave of items stays full; measured with 4-wavefront items at 8
+// rounds allowed: 256 blocks best at 2, 512 at 4, 1024 at 8).  Groups of
+// rounds start at rounds 1, 1 + M, 1 + 2 M, ...; a power of two, M divides
+// every other bunch's M or is a multiple of it.  Depends only on the bunch's
+// size and the tuning.
 __host__ __device__ inline int sym_rounds_for(int64_t nbk, int sym_rounds) {
-  return nbk >= 32 * (int64_t)sym_rounds ? sym_rounds : 1;
+  int m = sym_rounds;
+  while (m > 1 && nbk < 128 * (int64_t)m) m >>= 1;
+  return m;
 }
 
 // Rounds of the group that starts at round r (r >= 1, (r - 1) % M == 0) for

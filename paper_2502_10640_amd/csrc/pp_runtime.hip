@@ -980,10 +980,11 @@ pp_tuning default_tuning(bool mixed, const std::vector<pp_bunch>& hb, int cus) {
   t.graph_steps = 16;
   t.symmetric = 0;
   t.sym_split = 1;
-  // 8 rounds per symmetric item where a bunch has 256 blocks or more
-  // (sym_rounds_for): at 1M particles the fold and the rest of the step
-  // outside the pair kernel 1.65 -> 1.19 ms (mixed), 4.9 -> 3.0 ms (FP64),
-  // the pair kernel unchanged (`bench.py --tuning sym_rounds=1` against 8)
+  // up to 8 rounds per symmetric item (sym_rounds_for: 2 from 256 blocks, 4
+  // from 512, 8 from 1024): at 1M particles with 8-wavefront items the fold
+  // and the rest of the step outside the pair kernel went 1.65 -> 1.19 ms
+  // (mixed), 4.9 -> 3.0 ms (FP64); with 4-wavefront items 1M takes 1.2%
+  // less per step at 8 than at 1 (`bench.py --tuning sym_rounds=1` against 8)
   t.sym_rounds = 8;
   struct Variant { int k; double bs, eff; int blocks_per_cu; };
   std::vector<Variant> vars;

@@ -855,15 +855,16 @@ def test_simulation_calls_under_another_current_stream(orc, gpu):
 # several rounds per symmetric item (tuning field sym_rounds)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,M", [("mixed", 2), ("mixed", 4), ("fp64", 4), ("fp64", 8)])
-def test_sym_rounds_field_parity(orc, prec, M):
+@pytest.mark.parametrize("prec,M,n", [("mixed", 2, 70000), ("mixed", 4, 140000), ("fp64", 4, 140000),
+                                      ("fp64", 8, 270000)])
+def test_sym_rounds_field_parity(orc, prec, M, n):
     """Items sweeping M consecutive rounds (one receiver-side partial per
-    group of rounds): a 70000-particle bunch (274 blocks in either precision at
-    one receiver per lane, so the groups apply: at least 32 M blocks), a
-    small one that keeps one round per item, and a 5-particle one in one
-    batch; sampled receivers of the large bunch and every receiver of the
-    others against the oracle."""
-    big = wl.workload("gaussian_65536", n_override=70000)[0]
+    group of rounds): a large bunch with at least 128 M blocks at one receiver
+    per lane, so groups of M rounds apply (70000 particles: 274 blocks;
+    140000: 547; 270000: 1055), a small one that keeps one round per item,
+    and a 5-particle one in one batch; sampled receivers of the large bunch
+    and every receiver of the others against the oracle."""
+    big = wl.workload("gaussian_65536", n_override=n)[0]
     bunches = [big, wl.workload("cold_sphere_2048", n_override=3000)[0],
                wl.workload("cold_sphere_2048", n_override=5)[0]]
     tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "sym_split": 1, "sym_rounds": M,
@@ -884,8 +885,9 @@ def test_sym_rounds_field_parity(orc, prec, M):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_sym_rounds_bitwise_equivalences(prec):
-    """With 4 rounds per item: push == step_batched with graphs, and a batch
-    (one bunch with the groups, one without) equals the bunches alone."""
+    """With up to 4 rounds per item (2 for the 274-block bunch): push ==
+    step_batched with graphs, and a batch (one bunch with the groups, one
+    without) equals the bunches alone."""
     bunches = [wl.workload("gaussian_65536", n_override=70000)[0], wl.workload("gaussian_65536", n_override=2500)[0]]
     tun = {"symmetric": 1, "fused": 0, "i_per_lane": 1, "sym_split": 1, "sym_rounds": 4, "graph_steps": 2,
            "far_split": 3 if prec == "mixed" else 0}
