@@ -139,12 +139,13 @@ typedef struct {
   int32_t graph_steps;   /* steps captured per hipGraph with PP_GRAPH, 1..1024   */
   int32_t symmetric;     /* 1 evaluates each unordered pair once (Newton's
                             third law, Eq. (A) antisymmetry) in rounds of block
-                            pairs, i_per_lane 1, 2 or 4 (blocks of 512
-                            i_per_lane particles for PP_MIXED, 256 i_per_lane
-                            for PP_FP64); 0 evaluates every ordered pair in
-                            the ordered-pair kernel                             */
-  int32_t far_split;     /* PP_MIXED symmetric only: 0 keeps the hi/lo separations of
-                            Sec. 3 for every pair; f in 1..4 orders each bunch
+                            pairs, i_per_lane 1, 2 or 4 (blocks of 256
+                            i_per_lane particles in either precision); 0
+                            evaluates every ordered pair in the ordered-pair
+                            kernel                                              */
+  int32_t far_split;     /* PP_MIXED symmetric only: 0 keeps the hi/lo
+                            separations (positions as FP32 high + low parts)
+                            for every pair; f in 1..4 orders each bunch
                             along a Morton curve (recomputed at steps that are
                             multiples of 8, reused in between; the boxes below
                             always come from the current positions) and uses plain
