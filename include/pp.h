@@ -221,7 +221,11 @@ pp_status pp_create(pp_ctx **out, const pp_bunch *bunches, int32_t n_bunches, in
 /* Field (and optionally potential) at the current positions, Eq. (B) with
  * softening, written to caller-owned device arrays of length n_total (entries
  * outside every bunch are not written).  phi = NULL skips the potential; with
- * phi the self term j = i is excluded as in E.  Asynchronous. */
+ * phi the self term j = i is excluded as in E.  Two distinct particles at the
+ * same position contribute a zero term to each other when eps > 0; with
+ * eps = 0 their term is 0/0 as in Eq. (B) itself, so their field and
+ * potential are not finite (every other particle's are unaffected; the
+ * PP_CHECK flag of pp_step_batched reports such a state).  Asynchronous. */
 pp_status pp_field(pp_ctx *ctx, double *ex, double *ey, double *ez, double *phi);
 
 /* Allocation-free field of one bunch, without a context.  For callers that

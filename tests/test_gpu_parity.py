@@ -375,6 +375,44 @@ def test_nonfinite_is_detected_and_context_survives():
         assert not np.all(np.isfinite(sim.host("vx")))
 
 
+COINCIDENT_TILINGS = {
+    "ordered": ORDERED_TUNING,
+    "fused": {"symmetric": 0, "far_split": 0, "sym_split": 1, "fused": 8, "i_per_lane": 2},
+    "symmetric": {"symmetric": 1, "fused": 0, "i_per_lane": 1, "far_split": 0, "sym_split": 1},
+    "symmetric_far": {"symmetric": 1, "fused": 0, "i_per_lane": 2, "far_split": 3, "sym_split": 2},
+}
+
+
+@pytest.mark.parametrize("prec,sched", [(p, s) for p in PRECS for s in COINCIDENT_TILINGS
+                                         if not (s == "symmetric_far" and p == "fp64")])
+def test_coincident_particles(orc, prec, sched):
+    """Two pairs of particles at the same position, one pair inside a block
+    and one across blocks.  Softened, Eq. (B) is well defined there (the pair
+    term is zero): every field and potential equals the oracle's.  Without
+    softening the pair term is 0/0: exactly the four coincident particles get
+    a non-finite field and potential, and every other particle equals the
+    oracle's."""
+    b = wl.workload("cold_sphere_2048", n_override=3000)[0]
+    for i, j in ((3, 7), (10, 2500)):
+        b.x[j], b.y[j], b.z[j] = b.x[i], b.y[i], b.z[i]
+    bad = np.zeros(b.n, bool)
+    bad[[3, 7, 10, 2500]] = True
+    t = COINCIDENT_TILINGS[sched]
+    say(f"coincident particles {prec} {sched} n={b.n} eps={b.softening:.3e} and 0")
+    with Sim([b], prec, tuning=t) as sim:
+        got = gpu_field(sim)
+    check_field(got, oracle_field(orc, b), TOL[prec], f"coincident softened {sched}")
+    b.softening = 0.0
+    with Sim([b], prec, tuning=t) as sim:
+        got = gpu_field(sim)
+    ref = oracle_field(orc, b)
+    for key in ("ex", "ey", "ez", "phi"):
+        assert not np.any(np.isfinite(got[key][bad])), key
+        assert np.all(np.isfinite(got[key][~bad])), key
+    sub = lambda d: {key: v[~bad] for key, v in d.items()}
+    check_field(sub(got), sub(ref), TOL[prec], f"coincident unsoftened {sched}, the other particles")
+
+
 def test_device_side_validation():
     b = wl.workload("cold_sphere_2048", n_override=64)[0]
     say("create validates q and m on the device")
