@@ -62,9 +62,11 @@ __host__ __device__ inline double frame_scale(double h) {
 // Frame of the mixed path and the factors of the field and the potential of
 // one bunch from its set-up extents r[MM_LEN] (the same arithmetic on the host
 // and on the device): origin at the midpoint of the extent, scale
-// 2^-ceil(log2 half-extent) (at least the softening; exact), and, with
-// set_q, the reference charge (the charge of largest magnitude, 1 if all are
-// zero).  Returns whether the charges are all equal.
+// 2^-ceil(log2 half-extent) (at least the softening; exact; 1 when both are
+// zero, a bunch of one particle or of coincident ones, whose separations are
+// all zero in any frame), and, with set_q, the reference charge (the charge
+// of largest magnitude, 1 if all are zero).  Returns whether the charges are
+// all equal.
 __host__ __device__ inline bool frame_from_extents(const double* r, double weight, double softening, double kc,
                                                    bool mixed, bool set_q, BunchDev& B) {
 #pragma clang fp contract(off)
@@ -73,7 +75,8 @@ __host__ __device__ inline bool frame_from_extents(const double* r, double weigh
     B.origin[a] = 0.5 * (r[2 * a] + r[2 * a + 1]);
     half = fmax(half, 0.5 * (r[2 * a + 1] - r[2 * a]));
   }
-  half = fmax(fmax(half, softening), 1e-300);
+  half = fmax(half, softening);
+  if (!(half > 0.0)) half = 1.0;
   B.scale = frame_scale(half);
   const double qlo = r[MM_Q], qhi = r[MM_Q + 1];
   if (set_q) {

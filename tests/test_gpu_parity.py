@@ -413,6 +413,36 @@ def test_coincident_particles(orc, prec, sched):
     check_field(sub(got), sub(ref), TOL[prec], f"coincident unsoftened {sched}, the other particles")
 
 
+@pytest.mark.parametrize("prec,sched", [(p, s) for p in PRECS for s in COINCIDENT_TILINGS
+                                         if not (s == "symmetric_far" and p == "fp64")])
+def test_zero_extent_bunches(orc, prec, sched):
+    """Bunches with no extent: one particle with and without softening, and
+    three particles at one point with softening, in one batch beside an
+    ordinary bunch.  Their fields are exactly zero and so are the lone
+    particles' potentials (a zero extent must not blow up the mixed frame's
+    scale); the three coincident ones each see the potential 2 q / eps of the
+    other two, equal to the oracle's; the ordinary bunch's values are finite."""
+    lone = wl.workload("cold_sphere_2048", n_override=1)[0]
+    bare = wl.workload("cold_sphere_2048", n_override=1)[0]
+    bare.softening = 0.0
+    trio = wl.workload("cold_sphere_2048", n_override=3)[0]
+    for k in (1, 2):
+        trio.x[k], trio.y[k], trio.z[k] = trio.x[0], trio.y[0], trio.z[0]
+    other = wl.workload("cold_sphere_2048", n_override=700)[0]
+    bunches = [lone, bare, trio, other]
+    say(f"zero-extent bunches {prec} {sched}")
+    with Sim(bunches, prec, tuning=COINCIDENT_TILINGS[sched]) as sim:
+        got = gpu_field(sim)
+        slices = [sim.bunch_slice(i) for i in range(len(bunches))]
+    for i in range(3):
+        for key in ("ex", "ey", "ez") + (("phi",) if i < 2 else ()):
+            assert np.all(got[key][slices[i]] == 0.0), (i, key, got[key][slices[i]])
+    ref = oracle_field(orc, trio)["phi"]
+    np.testing.assert_allclose(got["phi"][slices[2]], ref, rtol=TOL[prec], atol=0)
+    for key in ("ex", "ey", "ez", "phi"):
+        assert np.all(np.isfinite(got[key][slices[3]]))
+
+
 def test_device_side_validation():
     b = wl.workload("cold_sphere_2048", n_override=64)[0]
     say("create validates q and m on the device")
