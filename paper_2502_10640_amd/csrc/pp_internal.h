@@ -66,7 +66,9 @@ __host__ __device__ inline double frame_scale(double h) {
 // zero, a bunch of one particle or of coincident ones, whose separations are
 // all zero in any frame), and, with set_q, the reference charge (the charge
 // of largest magnitude, 1 if all are zero).  Returns whether the charges are
-// all equal.
+// all equal and not zero: the uniform-charge kernels take every normalised
+// charge q / qref as 1, which a bunch of neutral particles (q / qref = 0) is
+// not.
 __host__ __device__ inline bool frame_from_extents(const double* r, double weight, double softening, double kc,
                                                    bool mixed, bool set_q, BunchDev& B) {
 #pragma clang fp contract(off)
@@ -95,7 +97,7 @@ __host__ __device__ inline bool frame_from_extents(const double* r, double weigh
     B.kPhi = kc * weight * qref;
     B.eps2 = softening * softening;
   }
-  return qlo == qhi;
+  return qlo == qhi && qlo != 0.0;
 }
 
 // Source chunks of one bunch of n particles in the ordered-pair work list

@@ -443,6 +443,30 @@ def test_zero_extent_bunches(orc, prec, sched):
         assert np.all(np.isfinite(got[key][slices[3]]))
 
 
+@pytest.mark.parametrize("prec,sched", [(p, s) for p in PRECS for s in COINCIDENT_TILINGS
+                                         if not (s == "symmetric_far" and p == "fp64")])
+def test_neutral_bunches(orc, prec, sched):
+    """Bunches whose particles carry no charge: alone, and in a batch beside a
+    bunch of equal charges (where the uniform-charge kernels would otherwise
+    apply).  Their fields and potentials are exactly zero; the charged
+    bunch's equal the oracle's."""
+    neutral = wl.workload("cold_sphere_2048", n_override=900)[0]
+    neutral.q[:] = 0.0
+    charged = wl.workload("cold_sphere_2048", n_override=1300)[0]
+    t = COINCIDENT_TILINGS[sched]
+    say(f"neutral bunches {prec} {sched}")
+    with Sim([neutral], prec, tuning=t) as sim:
+        alone = gpu_field(sim)
+    with Sim([neutral, charged], prec, tuning=t) as sim:
+        both = gpu_field(sim)
+        s0, s1 = sim.bunch_slice(0), sim.bunch_slice(1)
+    for key in ("ex", "ey", "ez", "phi"):
+        assert np.all(alone[key] == 0.0), key
+        assert np.all(both[key][s0] == 0.0), key
+    check_field({key: v[s1] for key, v in both.items()}, oracle_field(orc, charged), TOL[prec],
+                f"beside a neutral bunch {sched}")
+
+
 def test_device_side_validation():
     b = wl.workload("cold_sphere_2048", n_override=64)[0]
     say("create validates q and m on the device")
